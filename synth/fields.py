@@ -1,0 +1,259 @@
+"""Seeded synthetic skewer inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds no arithmetic of the optical-depth method: it only draws the
+input fields (overdensity Delta, peculiar velocity v, per-skewer pixel width,
+T0, gamma) and names the workload constants.  Both the FP64 oracle and the HIP
+library read its output; neither is imported here.
+
+Field recipe (pixel units, numpy ``Generator(PCG64(seed))``):
+
+* ``g``: a 1D Gaussian random field per skewer with power spectrum
+  P(k) ~ k^-1.5 for 0 < k <= 2 pi / (10 px) and zero above (sharp cutoff);
+  the k = 0 mode is zero.  White noise z ~ N(0, 1) per pixel, multiplied by
+  sqrt(P(k)) in Fourier space.  ``g`` is then scaled to unit sample variance
+  over the whole configuration.
+* ``ln Delta = sigma * g - sigma^2 / 2``, then ``Delta /= mean(Delta)`` over the
+  configuration, so that <Delta> = 1.
+* ``v``: correlated with the same field as in linear theory (the 1D analogue
+  of v(k) ~ i k / k^2 delta(k)): v(k) = i g(k) / k, scaled to a sample standard
+  deviation of 30 km/s over the configuration.
+
+The Gpc-scale shapes stand in for the paper's simulation boxes (4096-pixel
+sight-lines through a 4096^3 grid, 20,000-spectrum sets), whose rank-ordered
+density fields need a calibration hydrodynamical snapshot that is not
+available.  Fields are returned as float32, skewer-major, pixel fastest.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+K_CUT_PIX = 10.0  # cutoff wavelength of the field, in pixels
+PK_SLOPE = -1.5
+SIGMA_V = 30.0  # km/s
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    delta: np.ndarray      # float32 [P]
+    vpec: np.ndarray       # float32 [P], km/s
+    offsets: np.ndarray    # int64 [S+1]
+    dv: np.ndarray         # float32 [S], km/s per pixel
+    T0: np.ndarray         # float32 [S], K
+    gamma: np.ndarray      # float32 [S]
+    target_F: float
+    window_k: float
+    tau_ref: float = 1.0
+    delta_pivot: float = 10.0
+
+    @property
+    def n_skewers(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def n_pix(self) -> int:
+        return int(self.offsets[-1])
+
+    def subset(self, skewers) -> "Workload":
+        """Workload made of the listed skewers (same parameters)."""
+        idx = np.asarray(skewers, dtype=np.int64)
+        lens = self.offsets[idx + 1] - self.offsets[idx]
+        off = np.zeros(len(idx) + 1, np.int64)
+        off[1:] = np.cumsum(lens)
+        sel = np.concatenate([np.arange(self.offsets[s], self.offsets[s + 1])
+                              for s in idx]) if len(idx) else np.zeros(0, np.int64)
+        return dataclasses.replace(
+            self, name=f"{self.name}[subset {len(idx)}]",
+            delta=np.ascontiguousarray(self.delta[sel]),
+            vpec=np.ascontiguousarray(self.vpec[sel]), offsets=off,
+            dv=self.dv[idx].copy(), T0=self.T0[idx].copy(),
+            gamma=self.gamma[idx].copy())
+
+
+def _spectral_filters(n: int):
+    """sqrt(P(k)) and the velocity filter i/k on the rfft grid of length n."""
+    k = 2.0 * np.pi * np.fft.rfftfreq(n)  # radians per pixel
+    amp = np.zeros_like(k)
+    keep = (k > 0) & (k <= 2.0 * np.pi / K_CUT_PIX)
+    amp[keep] = k[keep] ** (PK_SLOPE / 2.0)
+    vfilt = np.zeros(k.shape, np.complex128)
+    vfilt[keep] = 1j / k[keep]
+    return amp, vfilt
+
+
+def gaussian_skewers(rng: np.random.Generator, lengths):
+    """Unnormalised (g, v) fields for skewers of the given lengths, drawn in
+    skewer order.  Returns two float64 arrays of size sum(lengths)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    P = int(lengths.sum())
+    g = np.empty(P)
+    v = np.empty(P)
+    uniq = np.unique(lengths)
+    if len(uniq) == 1 and len(lengths) > 0:
+        n = int(uniq[0])
+        z = rng.standard_normal((len(lengths), n))
+        amp, vf = _spectral_filters(n)
+        zk = np.fft.rfft(z, axis=1) * amp
+        g[:] = np.fft.irfft(zk, n=n, axis=1).ravel()
+        v[:] = np.fft.irfft(zk * vf, n=n, axis=1).ravel()
+        return g, v
+    filt = {int(n): _spectral_filters(int(n)) for n in uniq}
+    pos = 0
+    for n in lengths:
+        n = int(n)
+        z = rng.standard_normal(n)
+        amp, vf = filt[n]
+        zk = np.fft.rfft(z) * amp
+        g[pos:pos + n] = np.fft.irfft(zk, n=n)
+        v[pos:pos + n] = np.fft.irfft(zk * vf, n=n)
+        pos += n
+    return g, v
+
+
+def lognormal_fields(g: np.ndarray, v: np.ndarray, sigma_lnD: float,
+                     sigma_v: float = SIGMA_V):
+    """Normalise (g, v) over the configuration and exponentiate g."""
+    g = g / g.std()
+    lnD = sigma_lnD * g - 0.5 * sigma_lnD ** 2
+    D = np.exp(lnD)
+    D /= D.mean()
+    vs = v * (sigma_v / v.std()) if v.std() > 0 else v
+    return D.astype(np.float32), vs.astype(np.float32)
+
+
+def lognormal_skewers(lengths, sigma_lnD: float, seed: int,
+                      rng: np.random.Generator | None = None):
+    rng = rng if rng is not None else np.random.Generator(np.random.PCG64(seed))
+    g, v = gaussian_skewers(rng, lengths)
+    return lognormal_fields(g, v, sigma_lnD)
+
+
+def _offsets(lengths):
+    off = np.zeros(len(lengths) + 1, np.int64)
+    off[1:] = np.cumsum(lengths)
+    return off
+
+
+def uniform_workload(name, n_skewers, n_pix, dv, sigma_lnD, T0, gamma,
+                     target_F, window_k, seed, tau_ref=1.0, delta_pivot=10.0):
+    lengths = np.full(n_skewers, n_pix, np.int64)
+    D, v = lognormal_skewers(lengths, sigma_lnD, seed)
+    S = n_skewers
+    return Workload(name, D, v, _offsets(lengths),
+                    np.full(S, dv, np.float32), np.full(S, T0, np.float32),
+                    np.full(S, gamma, np.float32), target_F, window_k,
+                    tau_ref, delta_pivot)
+
+
+def ragged_workload(name, n_skewers, len_lo, len_hi, dv_lo, dv_hi, T0_lo,
+                    T0_hi, gamma_lo, gamma_hi, sigma_lnD, target_F, window_k,
+                    seed, tau_ref=1.0, delta_pivot=10.0):
+    """Skewers of uneven length.  Draw order: lengths, dv, T0, gamma (each a
+    vector over skewers), then the fields skewer by skewer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lengths = rng.integers(len_lo, len_hi + 1, size=n_skewers).astype(np.int64)
+    dv = rng.uniform(dv_lo, dv_hi, n_skewers).astype(np.float32)
+    T0 = rng.uniform(T0_lo, T0_hi, n_skewers).astype(np.float32)
+    gamma = rng.uniform(gamma_lo, gamma_hi, n_skewers).astype(np.float32)
+    D, v = lognormal_skewers(lengths, sigma_lnD, seed, rng=rng)
+    return Workload(name, D, v, _offsets(lengths), dv, T0, gamma, target_F,
+                    window_k, tau_ref, delta_pivot)
+
+
+# --------------------------------------------------------------------------
+# The five workloads.  "C1 statistics" = sigma_lnD 1.0, dv 2 km/s,
+# T0 1.5e4 K, gamma 1.5, target mean flux 0.8.
+
+def config1(seed: int = 1) -> Workload:
+    """64 skewers x 1024 px, dv 2 km/s (box 2048 km/s), sigma_lnD 1.0,
+    T0 1.5e4 K, gamma 1.5, target <F> 0.8; full-sum reference."""
+    return uniform_workload("C1 64x1024", 64, 1024, 2.0, 1.0, 1.5e4, 1.5, 0.8,
+                            6.0, seed)
+
+
+def config2(seed: int = 2) -> Workload:
+    """4096 skewers x 4096 px, dv 2 km/s, sigma_lnD 1.2, T0 2e4 K, gamma 1.3,
+    target <F> 0.75, window +-6 b."""
+    return uniform_workload("C2 4096x4096", 4096, 4096, 2.0, 1.2, 2.0e4, 1.3,
+                            0.75, 6.0, seed)
+
+
+def config3(seed: int = 3, n_skewers: int = 20000) -> Workload:
+    """20000 skewers, lengths uniform in [512, 8192] px, dv uniform in [1, 4]
+    km/s, T0 uniform in [1e4, 2.5e4] K, gamma uniform in [1.1, 1.6];
+    sigma_lnD 1.0 and target <F> 0.8 (C1 statistics)."""
+    return ragged_workload(f"C3 ragged {n_skewers}", n_skewers, 512, 8192,
+                           1.0, 4.0, 1.0e4, 2.5e4, 1.1, 1.6, 1.0, 0.8, 6.0,
+                           seed)
+
+
+def config5(seed: int = 5) -> Workload:
+    """4096 skewers x 2048 px with C1 statistics (adjoint workload)."""
+    return uniform_workload("C5 4096x2048", 4096, 2048, 2.0, 1.0, 1.5e4, 1.5,
+                            0.8, 6.0, seed)
+
+
+def small_workload(n_skewers=8, n_pix=256, seed=11, sigma_lnD=1.0, dv=2.0,
+                   T0=1.5e4, gamma=1.5, target_F=0.8, window_k=6.0):
+    return uniform_workload(f"small {n_skewers}x{n_pix}", n_skewers, n_pix, dv,
+                            sigma_lnD, T0, gamma, target_F, window_k, seed)
+
+
+def lognormal_box_3d(nx: int, ny: int, nz: int, sigma_lnD: float, seed: int,
+                     device="cpu", sigma_v: float = SIGMA_V):
+    """3D lognormal field of nx*ny skewers of nz pixels (skewer axis z,
+    contiguous), 3D P(k) ~ k^-1.5 with a sharp cutoff at 2 pi / (10 px), the
+    velocity along z from v(k) = i k_z / k^2 g(k), generated with torch.fft on
+    ``device`` (a seeded torch.Generator draws the white noise).  Returns
+    float32 torch tensors (Delta, v) of shape [nx*ny*nz]."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    z = torch.randn((nx, ny, nz), generator=gen, device=device,
+                    dtype=torch.float32)
+    zk = torch.fft.rfftn(z)
+    del z
+    kx = 2 * np.pi * torch.fft.fftfreq(nx, device=device)
+    ky = 2 * np.pi * torch.fft.fftfreq(ny, device=device)
+    kz = 2 * np.pi * torch.fft.rfftfreq(nz, device=device)
+    k2 = (kx[:, None, None] ** 2 + ky[None, :, None] ** 2
+          + kz[None, None, :] ** 2)
+    kmag = torch.sqrt(k2)
+    keep = (kmag > 0) & (kmag <= 2 * np.pi / K_CUT_PIX)
+    amp = torch.where(keep, kmag.clamp_min(1e-30) ** (PK_SLOPE / 2.0),
+                      torch.zeros_like(kmag))
+    del kmag
+    zk *= amp
+    del amp
+    vf = torch.where(keep, kz[None, None, :] / k2.clamp_min(1e-30),
+                     torch.zeros_like(k2))
+    del k2, keep
+    vk = zk * (1j * vf)
+    del vf
+    g = torch.fft.irfftn(zk, s=(nx, ny, nz))
+    del zk
+    v = torch.fft.irfftn(vk, s=(nx, ny, nz))
+    del vk
+    g = g / g.double().std().float()
+    lnD = sigma_lnD * g - 0.5 * sigma_lnD ** 2
+    del g
+    D = torch.exp(lnD)
+    del lnD
+    D = D / D.double().mean().float()
+    v = v * (sigma_v / v.double().std().float())
+    return D.reshape(-1).contiguous(), v.reshape(-1).contiguous()
+
+
+def config4(seed: int = 4, nx: int = 512, ny: int = 512, nz: int = 4096,
+            device="cpu") -> Workload:
+    """512 x 512 skewers of 4096 px through one seeded 3D lognormal field
+    (C1 statistics); arrays stay torch tensors on ``device``."""
+    D, v = lognormal_box_3d(nx, ny, nz, 1.0, seed, device=device)
+    S = nx * ny
+    lengths = np.full(S, nz, np.int64)
+    return Workload(f"C4 box {nx}x{ny}x{nz}", D, v, _offsets(lengths),
+                    np.full(S, 2.0, np.float32), np.full(S, 1.5e4, np.float32),
+                    np.full(S, 1.5, np.float32), 0.8, 6.0)
