@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the Lyman-alpha optical-depth hot path on one MI355X.
+
+One step = the whole path over the 4096 x 4096 workload (4096 skewers of 4096
+pixels, dv = 2 km/s, sigma_lnDelta = 1.2, T0 = 2e4 K, gamma = 1.3, window
++-6 b, target <F> = 0.75; synthetic lognormal fields, seed 2) with the inputs
+resident in HBM: lyaf_tau (per-skewer reach pass + windowed tau kernel), then
+lyaf_normalise_mean_flux (FP64 root-find passes + tau' = A tau, F = exp(-tau')).
+
+Prints one JSON line.  ``value`` is skewer-pixels per second of tau + F.
+``roofline`` describes the tau stage (the dominant kernel): algorithmic
+pairs inside the +-k b window (counted exactly from the inputs) times 7
+operations per pair (6 FP32 flops and one exp2), divided by the stage's
+average duration measured with HIP events on its stream, against the FP32
+vector peak of 157.3 TFLOP/s.  ``cpu_baseline`` is the FP64 oracle (full sum
++ root-find) on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("skewer-pixels/sec of τ+F at stated FP32 error vs FP64 oracle; roofline %")
+FP32_PEAK_TFLOPS = 157.3      # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
+OPS_PER_PAIR = 7              # fma (2) + mul (1) + square (1) + exp2 (1) + fma (2)
+HBM_PEAK_GBPS = 8000.0
+
+
+def algorithmic_pairs(w) -> float:
+    """sum over sources j of #{i : |(i - j) dv - v_j| < k b_j}, clamped to N,
+    with b_j from the T-rho relation (FP64, host)."""
+    kB, mH = 1.380649e-16, 1.6735575e-24
+    total = 0.0
+    lens = np.diff(w.offsets)
+    for s0 in range(0, w.n_skewers, 256):
+        s1 = min(w.n_skewers, s0 + 256)
+        a, b = int(w.offsets[s0]), int(w.offsets[s1])
+        d = w.delta[a:b].astype(np.float64)
+        v = w.vpec[a:b].astype(np.float64)
+        sk = np.repeat(np.arange(s0, s1), lens[s0:s1])
+        dv, T0, gm = (w.dv[sk].astype(np.float64), w.T0[sk].astype(np.float64),
+                      w.gamma[sk].astype(np.float64))
+        D = np.minimum(d, w.delta_pivot)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            T = T0 * np.where(D > 0, D, 1.0) ** (gm - 1)
+        bj = np.sqrt(2 * kB * T / mH) / 1e5
+        h = w.window_k * bj / dv
+        c = v / dv
+        # count integers m with c - h < m < c + h
+        cnt = np.ceil(c + h) - np.floor(c - h) - 1
+        cnt = np.minimum(np.maximum(cnt, 0), lens[sk])
+        total += float(np.where(d > 0, cnt, 0).sum())
+    return total
+
+
+def cpu_baseline(w, target_seconds=10.0):
+    """FP64 oracle on the host: full sum of eq. (6) + mean-flux root-find, on
+    the first skewers of the workload, sized to ~target_seconds of wall time."""
+    from oracle import oracle as O
+    n = 8
+    t_run = 0.0
+    while True:
+        sub = w.subset(range(n))
+        t0 = time.perf_counter()
+        raw = O.tau(sub.delta, sub.vpec, sub.dv, sub.T0, sub.gamma, offsets=sub.offsets,
+                    tau_ref=sub.tau_ref, delta_pivot=sub.delta_pivot)
+        O.normalise(raw, sub.target_F)
+        t_run = time.perf_counter() - t0
+        if t_run >= target_seconds / 4 or n >= w.n_skewers:
+            break
+        n = min(w.n_skewers, max(2 * n, int(n * target_seconds / 4 / max(t_run, 1e-3))))
+    return {"value": sub.n_pix / t_run, "unit": "skewer-pixels/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"first {n} skewers of the workload ({sub.n_pix} px), FP64 full "
+                      f"O(N^2) sum + root-find, {t_run:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this path runs on one GPU; --gpus N > 1 is not "
+                          "supported (skewers shard trivially, see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1105_4747_amd import lyaf as L
+    from synth import fields
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    L.load()
+    dev = torch.device("cuda:0")
+    w = getattr(fields, args.workload)()
+    print(f"bench: workload {w.name}, P={w.n_pix}", file=sys.stderr, flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    delta, vpec, dvt, T0, gamma = t(w.delta), t(w.vpec), t(w.dv), t(w.T0), t(w.gamma)
+    P = w.n_pix
+    raw = torch.empty(P, device=dev, dtype=torch.float32)
+    F = torch.empty(P, device=dev, dtype=torch.float32)
+    A = torch.empty((), device=dev, dtype=torch.float64)
+    stream = torch.cuda.current_stream()
+
+    def tau_stage(out):
+        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, out, tau_ref=w.tau_ref,
+              delta_pivot=w.delta_pivot, window_k=w.window_k)
+
+    def step():
+        tau_stage(raw)
+        L.normalise_mean_flux(raw, F, w.target_F, A)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if L.status_read() != 0:
+        raise RuntimeError("device status set during warmup")
+
+    # timed region: exactly K steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = P * args.steps / elapsed
+    print(f"bench: {ms_per_step:.4f} ms/step, {value:.4e} px/s", file=sys.stderr, flush=True)
+
+    # tau stage alone, HIP events on the launch stream
+    reps = max(args.steps, 10)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        tau_stage(raw)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_tau = ev0.elapsed_time(ev1) / reps * 1e-3
+    ev0.record(stream)
+    for _ in range(reps):
+        tmp = raw.clone()
+        L.normalise_mean_flux(tmp, F, w.target_F, A)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_norm = ev0.elapsed_time(ev1) / reps * 1e-3
+    pairs = algorithmic_pairs(w)
+    achieved = pairs * OPS_PER_PAIR / t_tau / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": None,
+                "kernel": "lyaf_tau (reach_kernel + tau_window_kernel)",
+                "kernel_ms": round(t_tau * 1e3, 4),
+                "pairs_per_launch": pairs, "pairs_per_px": round(pairs / P, 3),
+                "pair_rate_per_s": pairs / t_tau, "ops_per_pair": OPS_PER_PAIR}
+    extra = {"tau_stage_ms": round(t_tau * 1e3, 4),
+             "normalise_stage_ms_incl_copy": round(t_norm * 1e3, 4)}
+
+    if not args.no_plain:
+        # the plain unbatched FP32 kernel (full O(N^2) sum, one launch per skewer)
+        plain = torch.empty_like(raw)
+        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, plain, tau_ref=w.tau_ref,
+              delta_pivot=w.delta_pivot, window_k=w.window_k, flags=L.FLAG_PLAIN)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, plain, tau_ref=w.tau_ref,
+              delta_pivot=w.delta_pivot, window_k=w.window_k, flags=L.FLAG_PLAIN)
+        ev1.record(stream)
+        ev1.synchronize()
+        t_plain = ev0.elapsed_time(ev1) * 1e-3
+        extra["plain_fp32_tau_px_per_s"] = P / t_plain
+        extra["plain_fp32_tau_ms"] = round(t_plain * 1e3, 3)
+        extra["speedup_tau_vs_plain"] = round(t_plain / t_tau, 2)
+        del plain
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "skewer-pixels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_skewers": w.n_skewers, "n_pix": P,
+                   "dv_kms": float(w.dv[0]), "T0": float(w.T0[0]), "gamma": float(w.gamma[0]),
+                   "window_k": w.window_k, "target_F": w.target_F,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "detail": extra,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

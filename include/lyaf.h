@@ -1,0 +1,164 @@
+/*
+ * lyaf.h -- C ABI of the MI355X (gfx950) Lyman-alpha optical-depth library.
+ *
+ * The library computes, for a batch of sight-lines ("skewers") of gridded
+ * overdensity Delta and peculiar velocity v, the Lyman-alpha optical depth of
+ * Greig, Bolton & Wyithe (2011), Section 2.3:
+ *
+ *   T_j   = T0 * D_j^(gamma-1),  D_j = min(Delta_j, delta_pivot)   (eq. 5 + pivot)
+ *   b_j   = sqrt(2 k_B T_j / m_H)                                  (after eq. 6)
+ *   w_j   = tau_ref * Delta_j^2 * (T_j / 1e4 K)^-0.7 * dv / (sqrt(pi) b_j)
+ *                                                    (eq. 4 inside eq. 6)
+ *   tau_i = sum_j w_j * exp(-(d_ij / b_j)^2),  d_ij = (i - j) dv - v_j   (eq. 6)
+ *
+ * with d_ij taken at its minimal periodic image in a box of width V = N dv, and
+ * then the mean-flux renormalisation of Section 2.3: A solves
+ * (1/P) sum_p exp(-A tau_p) = target_F over every pixel of every skewer,
+ * tau' = A tau and F = exp(-tau').
+ *
+ * tau_ref folds every constant of eq. (4) and the prefactor c sigma_alpha
+ * deltaR / sqrt(pi) of eq. (6): it is the optical depth of a uniform field at
+ * Delta = 1 and T = 1e4 K.  Because the mean-flux rescale absorbs any constant
+ * factor, tau_ref only sets the scale of the raw tau.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers marked DEVICE point to memory of the current HIP device, owned by
+ *   the caller (for example torch tensors).  Pointers marked HOST point to host
+ *   memory read during the call only.  The library never frees, reallocates or
+ *   keeps caller memory.
+ * - Layout: skewer s owns pixels offsets[s] .. offsets[s+1]-1 of every [P]
+ *   array (skewer-major, pixel fastest, contiguous).
+ * - `stream` is a hipStream_t passed as void*; NULL is the null stream.  All
+ *   work is enqueued on it; no call synchronises the host unless stated.
+ * - Return value: LYAF_OK (0) or a negative LYAF_E* code.  Every error a host
+ *   can see (null pointers, bad sizes or offsets, bad parameters) is reported
+ *   before anything is enqueued, and the outputs are then untouched.
+ * - Data errors that only the device can see (Delta < 0 or non-finite, v
+ *   non-finite, dv <= 0, T0 <= 0, gamma non-finite, tau < 0, no mean-flux
+ *   root) set bits in a sticky per-device status word (LYAF_STATUS_*), read
+ *   and cleared by lyaf_status_read.  Outputs are unspecified when it is set.
+ * - Outputs are overwritten, never accumulated into.
+ * - The library keeps per-device, per-stream workspaces (a few MB at most),
+ *   allocated on the first call that needs them and reused afterwards; calls
+ *   that overlap on one stream are ordered by the stream, calls on different
+ *   streams do not share workspace.
+ */
+#ifndef LYAF_H
+#define LYAF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define LYAF_OK 0
+#define LYAF_EINVAL -1   /* bad argument detected on the host */
+#define LYAF_EDOMAIN -2  /* value outside the model's domain (host-visible) */
+#define LYAF_ENOROOT -3  /* no mean-flux root exists */
+#define LYAF_ENOCONV -4  /* root-find did not converge */
+#define LYAF_EDEVICE -5  /* a HIP runtime call failed */
+#define LYAF_ENOMEM -6   /* device allocation failed */
+
+/* ---- device status bits (lyaf_status_read) ---- */
+#define LYAF_STATUS_DOMAIN 1u  /* Delta<0, NaN/Inf input, dv<=0, T0<=0, tau<0 */
+#define LYAF_STATUS_NOROOT 2u  /* fraction of tau == 0 pixels >= target_F */
+#define LYAF_STATUS_NOCONV 4u  /* mean-flux iteration hit its cap */
+
+/* ---- lyaf_params.flags ---- */
+/* Plain form: the full O(N^2) sum of eq. (6), one thread per pixel, naive
+ * FP32 accumulation, one launch per skewer.  The comparison baseline. */
+#define LYAF_FLAG_PLAIN 1u
+/* Launch the windowed kernel once per skewer instead of one batched launch. */
+#define LYAF_FLAG_PER_SKEWER 2u
+/* Windowed kernel with one exp per pair (no Gaussian recurrence). */
+#define LYAF_FLAG_DIRECT_EXP 4u
+
+typedef struct lyaf_skewers {
+  int64_t n_skewers;      /* S >= 0 */
+  const int64_t *offsets; /* HOST [S+1]: offsets[0] = 0, non-decreasing; P = offsets[S] */
+  const float *delta;     /* DEVICE [P]: Delta = 1 + delta_b >= 0 (0: empty pixel, no line) */
+  const float *vpec;      /* DEVICE [P]: peculiar velocity along the line of sight, km/s */
+  const float *dv;        /* DEVICE [S]: pixel width in velocity, km/s (> 0) */
+  const float *T0;        /* DEVICE [S]: temperature at mean density, K (> 0) */
+  const float *gamma;     /* DEVICE [S]: slope of the T-rho relation (finite; < 1 allowed) */
+} lyaf_skewers;
+
+typedef struct lyaf_params {
+  double tau_ref;     /* > 0: optical depth of Delta = 1, T = 1e4 K gas */
+  double delta_pivot; /* > 0: T is held at T(delta_pivot) above it (10 in the paper); +INF disables */
+  double window_k;    /* >= 0: sum only |d| < window_k * b (6 is exact to exp(-36) per term);
+                         0 = full sum over every source */
+  uint32_t flags;     /* LYAF_FLAG_* */
+} lyaf_params;
+
+/* Raw optical depth, eq. (6) with eqs. (4)-(5), for every pixel of every
+ * skewer (Section 2.3).  FP32 arithmetic with compensated accumulation.
+ *   tau_out: DEVICE [P] float, written.
+ * Errors: EINVAL (null pointer with P > 0, S < 0, bad offsets, tau_ref <= 0,
+ * delta_pivot <= 0, window_k < 0 or non-finite), EDEVICE, ENOMEM. */
+int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out,
+             void *stream);
+
+/* Mean-flux renormalisation (Section 2.3, last paragraph): solve
+ * (1/P) sum_p exp(-A tau_p) = target_F for A in FP64 on the device (safeguarded
+ * Newton/Halley from the Jensen lower bound, FP64 sums), then write
+ * tau' = A tau and F = exp(-tau').
+ *   tau_inout: DEVICE [n_pix] float; raw tau in, A*tau out (may not alias F_out).
+ *   F_out:     DEVICE [n_pix] float, written (may be NULL to skip).
+ *   A_dev:     DEVICE double, written with A.
+ * No host synchronisation: a missing root or a non-converged iteration is
+ * reported through the status word (A is then left at its last iterate).
+ * Errors: EINVAL (n_pix < 0, null pointers, target_F not in (0, 1)), EDEVICE,
+ * ENOMEM. */
+int lyaf_normalise_mean_flux(int64_t n_pix, float *tau_inout, float *F_out,
+                             double target_F, double *A_dev, void *stream);
+
+/* Backward of lyaf_normalise_mean_flux.  With G_p = dL/dtau'_p - F_p dL/dF_p:
+ *   implicit_A = 0: dL/dtau_p = A G_p (A held fixed)
+ *   implicit_A = 1: A re-solved at fixed mean flux (implicit differentiation):
+ *     dL/dtau_p = A G_p - A F_p (sum_q G_q tau_q) / (sum_q F_q tau_q)
+ *   tau_raw: DEVICE [n_pix] raw tau (before the rescale); A_dev: DEVICE double.
+ *   grad_F, grad_tau_scaled: DEVICE [n_pix] or NULL (= zero).
+ *   grad_tau_raw_out: DEVICE [n_pix], written.
+ * Errors: EINVAL, EDEVICE, ENOMEM. */
+int lyaf_normalise_mean_flux_backward(int64_t n_pix, const float *tau_raw,
+                                      const double *A_dev, const float *grad_F,
+                                      const float *grad_tau_scaled,
+                                      int implicit_A, float *grad_tau_raw_out,
+                                      void *stream);
+
+/* Adjoint of lyaf_tau (chain rule through eqs. 4-6).  For each source j, with
+ * x = d_ij / b_j and E = exp(-x^2), S0_j = sum_i g_i w_j E, S1_j = sum_i g_i w_j E x,
+ * S2_j = sum_i g_i w_j E x^2, Q_j = S2_j - 1.2 S0_j:
+ *   dL/dv_j     = 2 S1_j / b_j
+ *   dL/dDelta_j = [2 S0_j + (gamma - 1) [Delta_j <= delta_pivot] Q_j] / Delta_j
+ *   dL/dT0_s    = sum_{j in s} Q_j / T0_s
+ *   dL/dgamma_s = sum_{j in s} Q_j ln D_j
+ * (Delta_j = 0 gives 0.)  The same window as lyaf_tau is used.
+ *   grad_tau_raw: DEVICE [P] float (dL/dtau_raw).
+ *   grad_delta, grad_vpec: DEVICE [P] float, written.
+ *   grad_T0, grad_gamma: DEVICE [S] double, written (either may be NULL).
+ * Errors: as lyaf_tau. */
+int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm,
+                      const float *grad_tau_raw, float *grad_delta,
+                      float *grad_vpec, double *grad_T0, double *grad_gamma,
+                      void *stream);
+
+/* Read and clear the device status word of the current device's workspace
+ * for `stream`.  Synchronises `stream`.  *device_status receives LYAF_STATUS_*
+ * bits accumulated since the last read. */
+int lyaf_status_read(void *stream, uint32_t *device_status);
+
+/* Human-readable name of a return code (static string). */
+const char *lyaf_strerror(int code);
+
+/* Library version, as MAJOR*10000 + MINOR*100 + PATCH. */
+int lyaf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LYAF_H */

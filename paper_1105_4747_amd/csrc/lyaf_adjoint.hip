@@ -1,0 +1,196 @@
+// lyaf_adjoint.hip -- hand-written adjoint of the optical-depth sum (Greig,
+// Bolton & Wyithe 2011, Section 2.3, eqs. 4-6), by the chain rule.
+//
+// For source j (weight w_j, Doppler parameter b_j, t = d_ij sqrt(log2 e) / b_j,
+// so that exp(-x^2) = exp2(-t^2) with x = d_ij / b_j):
+//   S0_j = w_j sum_i g_i E_ij,  S1_j = w_j sum_i g_i E_ij x_ij,
+//   S2_j = w_j sum_i g_i E_ij x_ij^2,  Q_j = S2_j - 1.2 S0_j,
+//   dL/dv_j = 2 S1_j / b_j,
+//   dL/dDelta_j = [2 S0_j + (gamma-1) [Delta_j <= pivot] Q_j] / Delta_j,
+//   dL/dT0 = sum_j Q_j / T0,   dL/dgamma = sum_j Q_j ln D_j.
+// The 1.2 is the temperature exponent of w (n_HI ~ T^-0.7 over b ~ T^0.5).
+//
+// Layout mirrors the forward: one workgroup per 256-source tile; the target
+// gradients g_i within reach are staged in LDS; each lane owns one source and
+// each wave walks the union of its 64 sources' windows, reading g_i as a
+// broadcast.  Short or wide skewers sum over every target with the minimal
+// image chosen per pair.  Per-skewer T0/gamma terms are summed in FP64 per
+// workgroup and then per skewer in a fixed order.
+#include <math.h>
+
+#include "lyaf_internal.h"
+
+namespace lyaf {
+
+__device__ __forceinline__ float aexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float alog2(float x) { return __builtin_amdgcn_logf(x); }
+
+constexpr int kAdjThreads = 256;
+constexpr int kAdjTile = 256;  // sources per workgroup
+
+__global__ __launch_bounds__(kAdjThreads) void tau_adjoint_kernel(
+    Batch b, const int2 *__restrict__ items, const float *__restrict__ g,
+    float *__restrict__ gdelta, float *__restrict__ gvpec, double *__restrict__ gpart) {
+  __shared__ float gl[kChunk];
+  __shared__ double shd[8];
+  const int2 item = items[blockIdx.x];
+  const int64_t s = item.x;
+  const int j0 = item.y * kAdjTile;
+  const SkewerConst K = b.skc[s];
+  const int64_t off = b.offsets[s];
+  const int n = K.n;
+  const int R = K.reach;
+  const int j = j0 + (int)threadIdx.x;
+  const bool valid = j < n;
+
+  // this lane's source
+  float delta = 0.f, v = 0.f, w = 0.f, r = K.R, bj = 0.f, l2D = 0.f;
+  if (valid) {
+    delta = b.delta[off + j];
+    v = b.vpec[off + j];
+    if (delta > 0.f) {
+      const float D = fmaxf(fminf(delta, b.pivot), 1e-30f);
+      l2D = alog2(D);
+      const float x = K.gm1 * l2D;
+      w = K.W * delta * delta * aexp2(kTempExpW * x);
+      r = K.R * aexp2(kTempExpR * x);
+      bj = K.B * aexp2(0.5f * x);
+    }
+  }
+  const float dv = K.dv;
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // sums of g E, g E t, g E t^2
+
+  const int e_lo = j0 - R;
+  const int e_hi = j0 + kAdjTile + R;
+  const int cnt = e_hi - e_lo;
+  if (cnt <= n && cnt <= kChunk) {
+    // windowed: targets e_lo .. e_hi-1 (extended, periodic)
+    for (int c = threadIdx.x; c < cnt; c += kAdjThreads) {
+      const int e = e_lo + c;
+      const int i = e < 0 ? e + n : (e >= n ? e - n : e);
+      gl[c] = g[off + i];
+    }
+    __syncthreads();
+    // union of this wave's windows, in local target index c = e - e_lo
+    float lo = INFINITY, hi = -INFINITY;
+    if (w > 0.f) {
+      const float cc = (float)j + v * K.inv_dv;
+      const float h = b.window_k * bj * K.inv_dv;
+      lo = cc - h - 1.f;
+      hi = cc + h + 1.f;
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, m));
+      hi = fmaxf(hi, __shfl_xor(hi, m));
+    }
+    if (lo <= hi) {
+      const int c_first = max(0, (int)floorf(lo) - e_lo);
+      const int c_last = min(cnt - 1, (int)ceilf(hi) - e_lo);
+      float fd = (float)(e_lo + c_first - j);  // target - source, exact
+      for (int c = c_first; c <= c_last; ++c) {
+        const float gi = gl[c];
+        const float d = __builtin_fmaf(fd, dv, -v);
+        const float t = d * r;
+        const float gE = gi * aexp2(-(t * t));
+        const float gEt = gE * t;
+        S0 += gE;
+        S1 += gEt;
+        S2 = __builtin_fmaf(gEt, t, S2);
+        fd += 1.f;
+      }
+    }
+  } else {
+    // every target, minimal image per pair
+    const float nf = (float)n;
+    const float invV = 1.f / (nf * dv);
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+      const int cn = min(kChunk, n - c0);
+      __syncthreads();
+      for (int c = threadIdx.x; c < cn; c += kAdjThreads) gl[c] = g[off + c0 + c];
+      __syncthreads();
+      float fd = (float)(c0 - j);
+      for (int c = 0; c < cn; ++c) {
+        const float gi = gl[c];
+        const float d0 = __builtin_fmaf(fd, dv, -v);
+        const float img = floorf(__builtin_fmaf(d0, invV, 0.5f));
+        const float d = __builtin_fmaf(__builtin_fmaf(img, -nf, fd), dv, -v);
+        const float t = d * r;
+        const float gE = gi * aexp2(-(t * t));
+        const float gEt = gE * t;
+        S0 += gE;
+        S1 += gEt;
+        S2 = __builtin_fmaf(gEt, t, S2);
+        fd += 1.f;
+      }
+    }
+  }
+
+  // per-source outputs (t = x sqrt(log2 e): x = t / sqrt(log2 e))
+  double q_T0 = 0.0, q_gam = 0.0;
+  if (valid) {
+    float gd = 0.f, gv = 0.f;
+    if (w > 0.f) {
+      const float inv_s = (float)(1.0 / kSqrtLog2e);
+      const float s0 = w * S0;
+      const float s1 = w * S1 * inv_s;
+      const float s2 = w * S2 * (inv_s * inv_s);
+      const float Q = s2 - 1.2f * s0;
+      gv = 2.f * s1 / bj;
+      const float below = (delta <= b.pivot) ? 1.f : 0.f;
+      gd = (2.f * s0 + K.gm1 * below * Q) / delta;
+      q_T0 = (double)Q;
+      q_gam = (double)Q * ((double)l2D * kLn2);  // Q ln D
+    }
+    gdelta[off + j] = gd;
+    gvpec[off + j] = gv;
+  }
+  // FP64 workgroup sums of Q (for dL/dT0 after division by T0) and Q ln D
+  double a0 = q_T0, a1 = q_gam;
+  for (int m = 32; m >= 1; m >>= 1) {
+    a0 += __shfl_xor(a0, m);
+    a1 += __shfl_xor(a1, m);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    shd[wv] = a0;
+    shd[4 + wv] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    gpart[2 * (int64_t)blockIdx.x + 0] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
+    gpart[2 * (int64_t)blockIdx.x + 1] = (shd[4] + shd[5]) + (shd[6] + shd[7]);
+  }
+}
+
+// Per-skewer fixed-order sum of the workgroup partials.  Items of skewer s are
+// item_base[s] .. item_base[s+1]-1.
+__global__ void adjoint_skewer_sum_kernel(const double *__restrict__ gpart,
+                                          const int64_t *__restrict__ item_base,
+                                          const float *__restrict__ T0, int64_t S,
+                                          double *__restrict__ gT0,
+                                          double *__restrict__ ggamma) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double q = 0.0, ql = 0.0;
+  for (int64_t k = item_base[s]; k < item_base[s + 1]; ++k) {
+    q += gpart[2 * k + 0];
+    ql += gpart[2 * k + 1];
+  }
+  if (gT0) gT0[s] = q / (double)T0[s];
+  if (ggamma) ggamma[s] = ql;
+}
+
+hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
+                              const int64_t *item_base_dev, const float *g, float *gdelta,
+                              float *gvpec, double *gT0, double *ggamma, double *gpart,
+                              hipStream_t st) {
+  if (n_items > 0)
+    hipLaunchKernelGGL(tau_adjoint_kernel, dim3((unsigned)n_items), dim3(kAdjThreads), 0, st, b,
+                       items, g, gdelta, gvpec, gpart);
+  if (b.n_skewers > 0 && (gT0 || ggamma))
+    hipLaunchKernelGGL(adjoint_skewer_sum_kernel, dim3((unsigned)((b.n_skewers + 255) / 256)),
+                       dim3(256), 0, st, gpart, item_base_dev, b.T0, b.n_skewers, gT0, ggamma);
+  return hipGetLastError();
+}
+
+}  // namespace lyaf

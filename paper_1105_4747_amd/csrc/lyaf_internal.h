@@ -1,0 +1,105 @@
+// lyaf_internal.h -- declarations shared by the HIP translation units of liblyaf.
+//
+// Physical constants, per-skewer constants, workspace layout and the host-side
+// launchers that lyaf_api.hip calls.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lyaf.h"
+
+namespace lyaf {
+
+// ---------------------------------------------------------------------------
+// Constants.  beta = sqrt(2 k_B / m_H) in km s^-1 K^-1/2, with
+// k_B = 1.380649e-16 erg/K (CODATA 2018, exact) and m_H = 1.6735575e-24 g
+// (hydrogen atom), so that b = beta sqrt(T) is the thermal Doppler parameter of
+// Section 2.3 (b = 12.845 km/s at 1e4 K).
+constexpr double kBeta = 0.12845065404917816;
+constexpr double kSqrtLog2e = 1.2011224087864498;  // sqrt(1 / ln 2)
+constexpr double kSqrtPi = 1.7724538509055159;
+constexpr double kLn2 = 0.69314718055994531;
+constexpr double kLog2e = 1.4426950408889634;
+
+// Exponents of eq. (4): n_HI ~ Delta^2 T^-0.7, divided by b ~ T^0.5.
+constexpr float kTempExpW = -1.2f;  // d ln w / d ln T
+constexpr float kTempExpR = -0.5f;  // d ln (1/b) / d ln T
+
+// Tiling of the windowed optical-depth kernel.
+constexpr int kWave = 64;
+constexpr int kTauThreads = 256;   // 4 waves per workgroup
+constexpr int kTauTile = 256;      // targets per workgroup (one work item)
+constexpr int kGroup = 16;         // sources per skip group
+constexpr int kChunk = 1536;       // sources staged in LDS at once
+// Largest per-pixel step a = dv r of t = d / b * sqrt(log2 e) for which the
+// Gaussian recurrence is used (b > 1.2 dv); colder sources use one exp per pair.
+constexpr float kRecurrenceMaxStep = 1.0f;
+
+// Per-skewer constants, computed in FP64 by the reach kernel and rounded once.
+struct SkewerConst {
+  float W;       // tau_ref 1e4^0.7 dv / (sqrt(pi) beta) T0^-1.2 : w = W Delta^2 D^(-1.2(gamma-1))
+  float R;       // sqrt(log2 e) / (beta sqrt(T0))              : r = R D^(-0.5(gamma-1))
+  float B;       // beta sqrt(T0)                               : b = B D^(0.5(gamma-1))
+  float gm1;     // gamma - 1
+  float dv;      // pixel width (km/s)
+  float inv_dv;  // 1 / dv
+  int32_t reach; // max_j (|v_j| + k b_j) / dv, rounded up, plus margin (pixels)
+  int32_t n;     // pixels in the skewer
+};
+
+// Mean-flux root-find state (device).
+struct NormState {
+  double A, lo, hi;
+  double P, target;
+  int32_t iter, done, status;
+  int32_t pad;
+};
+
+// Per-(device, stream) workspace.
+struct Workspace {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  uint32_t *status = nullptr;       // sticky LYAF_STATUS_* bits
+  unsigned int *counter = nullptr;  // last-block-done counter
+  double *partials = nullptr;       // [kMaxPartialBlocks * 4]
+  NormState *norm = nullptr;
+  double *ratio = nullptr;          // backward-normalise scalar
+  // growable buffers
+  SkewerConst *skc = nullptr;  int64_t skc_cap = 0;
+  int64_t *offsets = nullptr;  int64_t off_cap = 0;
+  int2 *items = nullptr;       int64_t items_cap = 0;
+  int64_t *item_base = nullptr; int64_t ib_cap = 0;    // [S+1] first item of each skewer
+  double *gpart = nullptr;     int64_t gpart_cap = 0;  // adjoint per-item FP64 partials
+};
+constexpr int kMaxPartialBlocks = 2048;
+constexpr int kNormMaxIter = 10;
+
+// Kernel-side view of a skewer batch.
+struct Batch {
+  const float *delta, *vpec, *dv, *T0, *gamma;
+  const int64_t *offsets;  // device [S+1]
+  SkewerConst *skc;        // device [S]
+  int64_t n_skewers;
+  float tau_ref, pivot, window_k;
+  uint32_t *status;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (return hipError_t of the launch).
+hipError_t launch_reach(const Batch &b, hipStream_t st);
+hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items,
+                             float *tau, bool direct, hipStream_t st);
+hipError_t launch_tau_plain(const Batch &b, int64_t skewer, int64_t n, float *tau,
+                            hipStream_t st);
+hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F,
+                       double *A_dev, Workspace &ws, hipStream_t st);
+hipError_t launch_norm_backward(int64_t n_pix, const float *tau, const double *A_dev,
+                                const float *gF, const float *gT, int implicit_A,
+                                float *out, Workspace &ws, hipStream_t st);
+hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
+                              const int64_t *item_base_dev, const float *g,
+                              float *gdelta, float *gvpec, double *gT0,
+                              double *ggamma, double *gpart, hipStream_t st);
+
+}  // namespace lyaf

@@ -1,0 +1,243 @@
+"""ctypes binding of liblyaf.so (the C ABI in include/lyaf.h).
+
+Argument marshalling only: every step of the optical-depth path runs in the
+HIP kernels of the library.  Torch supplies device memory and the current
+stream.  If the library is missing or fails to load, every call raises.
+
+Functions mirror the C entry points:
+  tau(...)                         -> lyaf_tau
+  normalise_mean_flux(...)         -> lyaf_normalise_mean_flux
+  normalise_mean_flux_backward(...)-> lyaf_normalise_mean_flux_backward
+  tau_backward(...)                -> lyaf_tau_backward
+  status_read(...)                 -> lyaf_status_read
+and ``TauFlux`` wraps the forward (tau, rescale, F) and the hand-written
+adjoint as a torch.autograd.Function.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblyaf.so")
+
+LYAF_OK, LYAF_EINVAL, LYAF_EDOMAIN, LYAF_ENOROOT = 0, -1, -2, -3
+LYAF_ENOCONV, LYAF_EDEVICE, LYAF_ENOMEM = -4, -5, -6
+STATUS_DOMAIN, STATUS_NOROOT, STATUS_NOCONV = 1, 2, 4
+FLAG_PLAIN, FLAG_PER_SKEWER, FLAG_DIRECT_EXP = 1, 2, 4
+
+EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_backward",
+            "lyaf_tau_backward", "lyaf_status_read", "lyaf_strerror", "lyaf_version")
+
+
+class LyafError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str = ""):
+        super().__init__(f"{what}: {msg or code} (code {code})")
+        self.code = code
+
+
+class Skewers(ctypes.Structure):
+    _fields_ = [("n_skewers", ctypes.c_int64),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("delta", ctypes.c_void_p), ("vpec", ctypes.c_void_p),
+                ("dv", ctypes.c_void_p), ("T0", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tau_ref", ctypes.c_double), ("delta_pivot", ctypes.c_double),
+                ("window_k", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load liblyaf.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_1105_4747_amd/build.py "
+                "(hipcc, gfx950); there is no CPU fallback")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        PS, PP = ctypes.POINTER(Skewers), ctypes.POINTER(Params)
+        lib.lyaf_tau.argtypes = [PS, PP, vp, vp]
+        lib.lyaf_tau.restype = i32
+        lib.lyaf_normalise_mean_flux.argtypes = [i64, vp, vp, dbl, vp, vp]
+        lib.lyaf_normalise_mean_flux.restype = i32
+        lib.lyaf_normalise_mean_flux_backward.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp]
+        lib.lyaf_normalise_mean_flux_backward.restype = i32
+        lib.lyaf_tau_backward.argtypes = [PS, PP, vp, vp, vp, vp, vp, vp]
+        lib.lyaf_tau_backward.restype = i32
+        lib.lyaf_status_read.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        lib.lyaf_status_read.restype = i32
+        lib.lyaf_strerror.argtypes = [i32]
+        lib.lyaf_strerror.restype = ctypes.c_char_p
+        lib.lyaf_version.argtypes = []
+        lib.lyaf_version.restype = i32
+        _lib = lib
+        return lib
+
+
+def strerror(code: int) -> str:
+    return load().lyaf_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != LYAF_OK:
+        raise LyafError(rc, what, strerror(rc))
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _host_offsets(offsets):
+    """int64 host array of skewer offsets (numpy, list or CPU tensor)."""
+    if hasattr(offsets, "detach"):
+        offsets = offsets.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+
+
+def make_skewers(delta, vpec, dv, T0, gamma, offsets):
+    """Fill the C struct; the returned tuple keeps the host offsets alive."""
+    off = _host_offsets(offsets)
+    sk = Skewers(len(off) - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                 _ptr(delta), _ptr(vpec), _ptr(dv), _ptr(T0), _ptr(gamma))
+    return sk, off
+
+
+def make_params(tau_ref=1.0, delta_pivot=10.0, window_k=6.0, flags=0):
+    return Params(float(tau_ref), float(delta_pivot), float(window_k), int(flags))
+
+
+def tau(delta, vpec, dv, T0, gamma, offsets, out, tau_ref=1.0, delta_pivot=10.0,
+        window_k=6.0, flags=0, stream=None):
+    """lyaf_tau: raw optical depth into ``out`` (float32 device [P])."""
+    sk, _off = make_skewers(delta, vpec, dv, T0, gamma, offsets)
+    prm = make_params(tau_ref, delta_pivot, window_k, flags)
+    _check(load().lyaf_tau(ctypes.byref(sk), ctypes.byref(prm), _ptr(out), _stream(stream)),
+           "lyaf_tau")
+    return out
+
+
+def normalise_mean_flux(tau_inout, F_out, target_F, A_out, stream=None):
+    """lyaf_normalise_mean_flux: tau_inout <- A tau, F_out <- exp(-A tau),
+    A_out (float64 device scalar) <- A."""
+    _check(load().lyaf_normalise_mean_flux(tau_inout.numel(), _ptr(tau_inout), _ptr(F_out),
+                                           float(target_F), _ptr(A_out), _stream(stream)),
+           "lyaf_normalise_mean_flux")
+
+
+def normalise_mean_flux_backward(tau_raw, A, grad_F, grad_tau_scaled, implicit_A, out,
+                                 stream=None):
+    _check(load().lyaf_normalise_mean_flux_backward(
+        tau_raw.numel(), _ptr(tau_raw), _ptr(A), _ptr(grad_F), _ptr(grad_tau_scaled),
+        int(bool(implicit_A)), _ptr(out), _stream(stream)),
+        "lyaf_normalise_mean_flux_backward")
+
+
+def tau_backward(delta, vpec, dv, T0, gamma, offsets, grad_tau_raw, grad_delta, grad_vpec,
+                 grad_T0=None, grad_gamma=None, tau_ref=1.0, delta_pivot=10.0,
+                 window_k=6.0, flags=0, stream=None):
+    sk, _off = make_skewers(delta, vpec, dv, T0, gamma, offsets)
+    prm = make_params(tau_ref, delta_pivot, window_k, flags)
+    _check(load().lyaf_tau_backward(ctypes.byref(sk), ctypes.byref(prm), _ptr(grad_tau_raw),
+                                    _ptr(grad_delta), _ptr(grad_vpec), _ptr(grad_T0),
+                                    _ptr(grad_gamma), _stream(stream)),
+           "lyaf_tau_backward")
+
+
+def status_read(stream=None) -> int:
+    v = ctypes.c_uint32(0)
+    _check(load().lyaf_status_read(_stream(stream), ctypes.byref(v)), "lyaf_status_read")
+    return int(v.value)
+
+
+def version() -> int:
+    return int(load().lyaf_version())
+
+
+# ---------------------------------------------------------------------------
+def _autograd():
+    import torch
+
+    class TauFlux(torch.autograd.Function):
+        """(Delta, v, T0, gamma) -> (tau', F) with the mean-flux rescale.
+
+        forward : lyaf_tau, then lyaf_normalise_mean_flux.
+        backward: lyaf_normalise_mean_flux_backward (A implicit unless
+                  ``implicit_A`` is False), then lyaf_tau_backward.
+        T0 and gamma are per-skewer float32 tensors; their gradients come back
+        per skewer (the library sums them in FP64)."""
+
+        @staticmethod
+        def forward(ctx, delta, vpec, T0, gamma, dv, offsets, target_F, tau_ref,
+                    delta_pivot, window_k, implicit_A):
+            delta, vpec = delta.contiguous(), vpec.contiguous()
+            T0, gamma, dv = T0.contiguous(), gamma.contiguous(), dv.contiguous()
+            P = delta.numel()
+            raw = torch.empty(P, device=delta.device, dtype=torch.float32)
+            tau(delta, vpec, dv, T0, gamma, offsets, raw, tau_ref, delta_pivot, window_k)
+            ts = raw.clone()
+            F = torch.empty_like(raw)
+            A = torch.empty((), device=delta.device, dtype=torch.float64)
+            normalise_mean_flux(ts, F, target_F, A)
+            ctx.save_for_backward(delta, vpec, T0, gamma, dv, raw, A)
+            ctx.cfg = (offsets, tau_ref, delta_pivot, window_k, implicit_A)
+            ctx.mark_non_differentiable(A)
+            return ts, F, A
+
+        @staticmethod
+        def backward(ctx, g_ts, g_F, g_A):
+            delta, vpec, T0, gamma, dv, raw, A = ctx.saved_tensors
+            offsets, tau_ref, delta_pivot, window_k, implicit_A = ctx.cfg
+            g_raw = torch.empty_like(raw)
+            normalise_mean_flux_backward(
+                raw, A, None if g_F is None else g_F.contiguous().float(),
+                None if g_ts is None else g_ts.contiguous().float(), implicit_A, g_raw)
+            gd = torch.empty_like(delta)
+            gv = torch.empty_like(vpec)
+            gT = torch.empty(T0.numel(), device=T0.device, dtype=torch.float64)
+            gg = torch.empty(gamma.numel(), device=gamma.device, dtype=torch.float64)
+            tau_backward(delta, vpec, dv, T0, gamma, offsets, g_raw, gd, gv, gT, gg,
+                         tau_ref, delta_pivot, window_k)
+            return (gd, gv, gT.to(T0.dtype), gg.to(gamma.dtype), None, None, None, None,
+                    None, None, None)
+
+    return TauFlux
+
+
+_TauFlux = None
+
+
+def tau_flux(delta, vpec, T0, gamma, dv, offsets, target_F, tau_ref=1.0, delta_pivot=10.0,
+             window_k=6.0, implicit_A=True):
+    """Differentiable (tau', F, A) for torch tensors on the GPU."""
+    global _TauFlux
+    if _TauFlux is None:
+        _TauFlux = _autograd()
+    return _TauFlux.apply(delta, vpec, T0, gamma, dv, offsets, target_F, tau_ref,
+                          delta_pivot, window_k, implicit_A)
