@@ -73,8 +73,6 @@ extern "C" {
 #define LYAF_FLAG_PLAIN 1u
 /* Launch the windowed kernel once per skewer instead of one batched launch. */
 #define LYAF_FLAG_PER_SKEWER 2u
-/* Windowed kernel with one exp per pair (no Gaussian recurrence). */
-#define LYAF_FLAG_DIRECT_EXP 4u
 
 typedef struct lyaf_skewers {
   int64_t n_skewers;      /* S >= 0 */

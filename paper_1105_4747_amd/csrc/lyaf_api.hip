@@ -83,12 +83,10 @@ int get_ws(hipStream_t st, Workspace **out) {
   w->device = dev;
   w->stream = st;
   if ((e = hipMalloc((void **)&w->status, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMalloc((void **)&w->counter, sizeof(unsigned int))) != hipSuccess ||
       (e = hipMalloc((void **)&w->partials, sizeof(double) * 4 * kMaxPartialBlocks)) != hipSuccess ||
       (e = hipMalloc((void **)&w->norm, sizeof(NormState))) != hipSuccess ||
       (e = hipMalloc((void **)&w->ratio, sizeof(double))) != hipSuccess ||
       (e = hipMemset(w->status, 0, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMemset(w->counter, 0, sizeof(unsigned int))) != hipSuccess ||
       (e = hipMemset(w->norm, 0, sizeof(NormState))) != hipSuccess ||
       (e = hipMemset(w->ratio, 0, sizeof(double))) != hipSuccess) {
     delete w;
@@ -235,11 +233,9 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out, voi
   } else if (prm->flags & LYAF_FLAG_PER_SKEWER) {
     for (int64_t s = 0; s < S && e == hipSuccess; ++s)
       e = launch_tau_window(b, ws->items + hp->item_base[s],
-                            hp->item_base[s + 1] - hp->item_base[s], tau_out,
-                            (prm->flags & LYAF_FLAG_DIRECT_EXP) != 0, st);
+                            hp->item_base[s + 1] - hp->item_base[s], tau_out, st);
   } else {
-    e = launch_tau_window(b, ws->items, hp->n_items, tau_out,
-                          (prm->flags & LYAF_FLAG_DIRECT_EXP) != 0, st);
+    e = launch_tau_window(b, ws->items, hp->n_items, tau_out, st);
   }
   return map_err(e);
 }

@@ -32,9 +32,6 @@ constexpr int kTauThreads = 256;   // 4 waves per workgroup
 constexpr int kTauTile = 256;      // targets per workgroup (one work item)
 constexpr int kGroup = 16;         // sources per skip group
 constexpr int kChunk = 1536;       // sources staged in LDS at once
-// Largest per-pixel step a = dv r of t = d / b * sqrt(log2 e) for which the
-// Gaussian recurrence is used (b > 1.2 dv); colder sources use one exp per pair.
-constexpr float kRecurrenceMaxStep = 1.0f;
 
 // Per-skewer constants, computed in FP64 by the reach kernel and rounded once.
 struct SkewerConst {
@@ -61,7 +58,6 @@ struct Workspace {
   int device = -1;
   hipStream_t stream = nullptr;
   uint32_t *status = nullptr;       // sticky LYAF_STATUS_* bits
-  unsigned int *counter = nullptr;  // last-block-done counter
   double *partials = nullptr;       // [kMaxPartialBlocks * 4]
   NormState *norm = nullptr;
   double *ratio = nullptr;          // backward-normalise scalar
@@ -89,7 +85,7 @@ struct Batch {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_reach(const Batch &b, hipStream_t st);
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items,
-                             float *tau, bool direct, hipStream_t st);
+                             float *tau, hipStream_t st);
 hipError_t launch_tau_plain(const Batch &b, int64_t skewer, int64_t n, float *tau,
                             hipStream_t st);
 hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F,

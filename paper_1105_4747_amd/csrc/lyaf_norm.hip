@@ -7,11 +7,14 @@
 // and starts from the Jensen lower bound A0 = -ln F / <tau> (g(A0) >= 0, and g
 // is convex and decreasing, so Newton steps from the left never overshoot).
 // Each further pass (norm_moments) evaluates S_k = sum tau^k exp(-A tau),
-// k = 0, 1, 2, in FP64 and the last workgroup to finish applies a safeguarded
-// Halley step (Newton, then bisection, as fallbacks) inside the bracket.  A
-// fixed number of passes is enqueued; once converged the remaining ones
-// return at once.  Partial sums are combined in a fixed order, so results are
-// bitwise reproducible.
+// k = 0, 1, 2, in FP64 per workgroup; a one-workgroup kernel (norm_update)
+// sums the partials and applies a safeguarded Halley step (Newton, then
+// bisection, as fallbacks) inside the bracket.  A kernel boundary, not a
+// device-scope fence, publishes the partials: on a multi-XCD part a fence per
+// workgroup writes back and invalidates L2 and serialises the pass.  A fixed
+// number of passes is enqueued; once converged the remaining ones return at
+// once.  Partial sums are combined in a fixed order, so results are bitwise
+// reproducible.
 #include <math.h>
 
 #include "lyaf_internal.h"
@@ -61,21 +64,6 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *sh /*[N*4]*/) 
   __syncthreads();
 }
 
-// Last-workgroup-done: returns true in every thread of the workgroup that
-// finished last.  Partials must have been written before the call.
-__device__ __forceinline__ bool last_block(unsigned int *counter, int *flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    *flag = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *flag != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 // Fixed-order reduction of NQ partial quantities written per workgroup.
 template <int NQ>
 __device__ __forceinline__ void reduce_partials(const double *partials, int nblocks,
@@ -90,13 +78,10 @@ __device__ __forceinline__ void reduce_partials(const double *partials, int nblo
 
 constexpr int kNormThreads = 256;
 
+// Pass 0: sum tau, count tau == 0 and count invalid values, per workgroup.
 __global__ __launch_bounds__(kNormThreads) void norm_init_kernel(const float *__restrict__ tau,
-                                                                 int64_t P, double target,
-                                                                 NormState *st, double *partials,
-                                                                 unsigned int *counter,
-                                                                 uint32_t *status) {
+                                                                 int64_t P, double *partials) {
   __shared__ double sh[16];
-  __shared__ int flag;
   double v[3] = {0.0, 0.0, 0.0};  // sum tau, #zeros, #bad
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
@@ -113,11 +98,17 @@ __global__ __launch_bounds__(kNormThreads) void norm_init_kernel(const float *__
     partials[blockIdx.x * 4 + 1] = v[1];
     partials[blockIdx.x * 4 + 2] = v[2];
   }
-  if (!last_block(counter, &flag)) return;
+}
+
+// One workgroup: fixed-order sum of the init partials, starting state.
+__global__ __launch_bounds__(kNormThreads) void norm_start_kernel(int nblocks, int64_t P,
+                                                                  double target, NormState *st,
+                                                                  const double *partials,
+                                                                  uint32_t *status) {
+  __shared__ double sh[16];
   double tot[3];
-  reduce_partials<3>(partials, gridDim.x, tot, sh);
+  reduce_partials<3>(partials, nblocks, tot, sh);
   if (threadIdx.x == 0) {
-    *counter = 0u;
     const double Pd = (double)P;
     NormState s;
     s.P = Pd;
@@ -141,13 +132,11 @@ __global__ __launch_bounds__(kNormThreads) void norm_init_kernel(const float *__
   }
 }
 
+// One pass: S_k = sum tau^k exp(-A tau), k = 0..2, per workgroup.
 __global__ __launch_bounds__(kNormThreads) void norm_moments_kernel(const float *__restrict__ tau,
-                                                                    int64_t P, NormState *st,
-                                                                    double *partials,
-                                                                    unsigned int *counter,
-                                                                    uint32_t *status) {
+                                                                    int64_t P, const NormState *st,
+                                                                    double *partials) {
   __shared__ double sh[16];
-  __shared__ int flag;
   if (st->done) return;  // converged (or failed) in an earlier pass
   const double A = st->A;
   double v[3] = {0.0, 0.0, 0.0};
@@ -190,11 +179,18 @@ __global__ __launch_bounds__(kNormThreads) void norm_moments_kernel(const float 
     partials[blockIdx.x * 4 + 1] = v[1];
     partials[blockIdx.x * 4 + 2] = v[2];
   }
-  if (!last_block(counter, &flag)) return;
+}
+
+// One workgroup: fixed-order sum of the moment partials and one safeguarded
+// Halley step inside the bracket.
+__global__ __launch_bounds__(kNormThreads) void norm_update_kernel(int nblocks, NormState *st,
+                                                                   const double *partials,
+                                                                   uint32_t *status) {
+  __shared__ double sh[16];
+  if (st->done) return;
   double tot[3];
-  reduce_partials<3>(partials, gridDim.x, tot, sh);
+  reduce_partials<3>(partials, nblocks, tot, sh);
   if (threadIdx.x == 0) {
-    *counter = 0u;
     NormState s = *st;
     const double g = tot[0] / s.P - s.target;  // g(A) = <exp(-A tau)> - F
     const double g1 = -tot[1] / s.P;           // g'(A)
@@ -253,10 +249,15 @@ hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F, dou
                        Workspace &ws, hipStream_t st) {
   const int grid = norm_grid(n_pix);
   hipLaunchKernelGGL(norm_init_kernel, dim3(grid), dim3(kNormThreads), 0, st, tau, n_pix,
-                     target_F, ws.norm, ws.partials, ws.counter, ws.status);
-  for (int it = 0; it < kNormMaxIter; ++it)
+                     ws.partials);
+  hipLaunchKernelGGL(norm_start_kernel, dim3(1), dim3(kNormThreads), 0, st, grid, n_pix,
+                     target_F, ws.norm, ws.partials, ws.status);
+  for (int it = 0; it < kNormMaxIter; ++it) {
     hipLaunchKernelGGL(norm_moments_kernel, dim3(grid), dim3(kNormThreads), 0, st, tau, n_pix,
-                       ws.norm, ws.partials, ws.counter, ws.status);
+                       ws.norm, ws.partials);
+    hipLaunchKernelGGL(norm_update_kernel, dim3(1), dim3(kNormThreads), 0, st, grid, ws.norm,
+                       ws.partials, ws.status);
+  }
   const int fgrid = (int)std::min<int64_t>((n_pix + 1023) / 1024 + 1, 65536);
   hipLaunchKernelGGL(norm_finalise_kernel, dim3(fgrid), dim3(kNormThreads), 0, st, tau, F,
                      n_pix, ws.norm, A_dev);
@@ -273,10 +274,8 @@ __device__ __forceinline__ void fwd_F(double A, float t, float &ts, float &Fp) {
 
 __global__ __launch_bounds__(kNormThreads) void normbw_reduce_kernel(
     const float *__restrict__ tau, const double *A_dev, const float *__restrict__ gF,
-    const float *__restrict__ gT, int64_t P, double *partials, unsigned int *counter,
-    double *ratio) {
+    const float *__restrict__ gT, int64_t P, double *partials) {
   __shared__ double sh[16];
-  __shared__ int flag;
   const double A = *A_dev;
   double v[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -292,13 +291,15 @@ __global__ __launch_bounds__(kNormThreads) void normbw_reduce_kernel(
     partials[blockIdx.x * 4 + 0] = v[0];
     partials[blockIdx.x * 4 + 1] = v[1];
   }
-  if (!last_block(counter, &flag)) return;
+}
+
+__global__ __launch_bounds__(kNormThreads) void normbw_ratio_kernel(int nblocks,
+                                                                    const double *partials,
+                                                                    double *ratio) {
+  __shared__ double sh[16];
   double tot[2];
-  reduce_partials<2>(partials, gridDim.x, tot, sh);
-  if (threadIdx.x == 0) {
-    *counter = 0u;
-    *ratio = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
-  }
+  reduce_partials<2>(partials, nblocks, tot, sh);
+  if (threadIdx.x == 0) *ratio = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
 }
 
 __global__ __launch_bounds__(kNormThreads) void normbw_apply_kernel(
@@ -321,9 +322,12 @@ hipError_t launch_norm_backward(int64_t n_pix, const float *tau, const double *A
                                 const float *gF, const float *gT, int implicit_A, float *out,
                                 Workspace &ws, hipStream_t st) {
   const int grid = norm_grid(n_pix);
-  if (implicit_A)
+  if (implicit_A) {
     hipLaunchKernelGGL(normbw_reduce_kernel, dim3(grid), dim3(kNormThreads), 0, st, tau, A_dev,
-                       gF, gT, n_pix, ws.partials, ws.counter, ws.ratio);
+                       gF, gT, n_pix, ws.partials);
+    hipLaunchKernelGGL(normbw_ratio_kernel, dim3(1), dim3(kNormThreads), 0, st, grid,
+                       ws.partials, ws.ratio);
+  }
   const int fgrid = (int)std::min<int64_t>((n_pix + 1023) / 1024 + 1, 65536);
   hipLaunchKernelGGL(normbw_apply_kernel, dim3(fgrid), dim3(kNormThreads), 0, st, tau, A_dev,
                      gF, gT, n_pix, ws.ratio, implicit_A, out);

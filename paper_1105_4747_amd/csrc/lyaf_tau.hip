@@ -4,17 +4,16 @@
 //   reach_kernel        one workgroup per skewer: per-skewer constants in FP64,
 //                       the largest velocity-space reach (|v_j| + k b_j) / dv in
 //                       pixels, and the device-side domain checks.
-//   tau_window_kernel   one workgroup per 256-pixel target tile.  The sources
-//                       that can reach the tile (tile +- reach) are staged once
-//                       into LDS as (w, r, v, a, Q) plus the window bounds of
-//                       every 16-source group.  Each wave splits into S source
-//                       streams of 64/S lanes; a lane owns M consecutive
-//                       targets and, per source, evaluates the first Gaussian
-//                       with one exp2 and the other M-1 with the exact
-//                       recurrence E_{k+1} = E_k R_k, R_{k+1} = R_k Q (the
-//                       exponent of eq. 6 is quadratic in the target index).
-//                       Streams sum in FP32 with a blocked Kahan fold and meet
-//                       in a butterfly across lanes at the end.
+//   tau_window_kernel   one workgroup per target tile.  The sources that can
+//                       reach the tile (tile +- reach) are staged once into
+//                       LDS as (w, r, v, a = dv r) plus the window bounds of
+//                       every group of S sources.  Each wave splits into S
+//                       source streams of 64/S lanes; a lane owns M
+//                       consecutive targets and evaluates, per source, one
+//                       exact FMA for the velocity offset and one exp2 per
+//                       pair.  A wave visits only the contiguous run of groups
+//                       whose windows reach its targets.  Streams sum in FP32
+//                       with a blocked Kahan fold and meet in a DPP butterfly.
 //                       Short or very wide skewers (tile + 2 reach > N) take a
 //                       full-sum path over every source with the minimal
 //                       periodic image chosen per pair.
@@ -169,43 +168,85 @@ __device__ void full_sum_tile(const Batch &b, const SkewerConst &K, int64_t off,
   if (i < n) tau[off + i] = sum;
 }
 
-// Windowed tile.  S source streams per wave, M consecutive targets per lane.
-template <int S, int M, bool DIRECT>
+// Lane permutations inside a row of 16 lanes (DPP), used to sum over the
+// source streams that share a set of targets.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7-i within each 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15-i within each 16 lanes
+
+template <int S>
+__device__ __forceinline__ float stream_sum(float x) {
+  static_assert(S == 4 || S == 8 || S == 16, "streams");
+  x += dpp<kDppXor1>(x);
+  x += dpp<kDppXor2>(x);
+  if (S >= 8) x += dpp<kDppHalfMirror>(x);
+  if (S >= 16) x += dpp<kDppMirror>(x);
+  return x;
+}
+template <int S>
+__device__ __forceinline__ float stream_min(float x) {
+  x = fminf(x, dpp<kDppXor1>(x));
+  x = fminf(x, dpp<kDppXor2>(x));
+  if (S >= 8) x = fminf(x, dpp<kDppHalfMirror>(x));
+  if (S >= 16) x = fminf(x, dpp<kDppMirror>(x));
+  return x;
+}
+template <int S>
+__device__ __forceinline__ float stream_max(float x) {
+  x = fmaxf(x, dpp<kDppXor1>(x));
+  x = fmaxf(x, dpp<kDppXor2>(x));
+  if (S >= 8) x = fmaxf(x, dpp<kDppHalfMirror>(x));
+  if (S >= 16) x = fmaxf(x, dpp<kDppMirror>(x));
+  return x;
+}
+
+// Windowed tile of TILE targets.  A wave is S source streams of 64/S lanes;
+// a lane owns M consecutive targets, so a wave sub-tile is (64/S)*M targets
+// and one loop iteration evaluates S sources (one skip group) against it.
+// Per source and lane: d0 = (i0 - j) dv - v_j exactly (one FMA on the integer
+// offset), t_k = d_k r_j = t_0 + k a_j (a_j = dv r_j), E_k = exp2(-t_k^2).
+template <int S, int M, int TILE>
 __global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
                                                                  const int2 *__restrict__ items,
                                                                  float *__restrict__ tau) {
+  constexpr int G = S;                   // sources per skip group = streams
   constexpr int L = kWave / S;           // lanes per stream
   constexpr int Tt = L * M;              // targets per wave sub-tile
   constexpr int NW = kTauThreads / kWave;
-  constexpr int SUB = kTauTile / (NW * Tt);
-  static_assert(SUB * NW * Tt == kTauTile, "tile shape");
-  static_assert(kGroup % S == 0, "streams must divide a group");
-  constexpr int KB = 16;                 // Kahan fold period (sources per stream)
+  constexpr int SUB = TILE / (NW * Tt);
+  constexpr int NG = kChunk / G;         // groups that fit in LDS
+  constexpr int NB = (NG + kWave - 1) / kWave;
+  static_assert(SUB * NW * Tt == TILE, "tile shape");
+  constexpr int KB = 16;                 // Kahan fold period (iterations)
 
-  __shared__ float4 rec[kChunk];
-  __shared__ float qrec[kChunk];
-  __shared__ float2 bnd[kChunk / kGroup];
-  __shared__ int gcold[kChunk / kGroup];
+  __shared__ float4 rec[kChunk + 2 * G];
+  __shared__ float2 bnd[NG];
 
   const int2 item = items[blockIdx.x];
   const int64_t s = item.x;
-  const int i0 = item.y * kTauTile;
+  const int i0 = item.y * TILE;
   const SkewerConst K = b.skc[s];
   const int64_t off = b.offsets[s];
   const int n = K.n;
   const int R = K.reach;
 
   int e_lo = i0 - R;
-  e_lo = (e_lo >= 0) ? (e_lo / kGroup) * kGroup : -(((-e_lo) + kGroup - 1) / kGroup) * kGroup;
-  int e_hi = i0 + kTauTile + R;
-  e_hi = ((e_hi + kGroup - 1) / kGroup) * kGroup;
+  e_lo = (e_lo >= 0) ? (e_lo / G) * G : -(((-e_lo) + G - 1) / G) * G;
+  int e_hi = i0 + TILE + R;
+  e_hi = ((e_hi + G - 1) / G) * G;
   const int cnt = e_hi - e_lo;
   if (cnt > n || cnt > kChunk) {  // the window covers the box: full sum
-    full_sum_tile<true>(b, K, off, i0, tau, rec);
+    for (int q = 0; q < TILE; q += kTauThreads)
+      full_sum_tile<true>(b, K, off, i0 + q, tau, rec);
     return;
   }
 
-  // ---- stage sources e_lo .. e_hi-1 (extended, periodic) with group bounds
+  // ---- stage sources e_lo .. e_hi-1 (extended, periodic) and group bounds
   const float pivot = b.pivot, wk = b.window_k;
   for (int c = threadIdx.x; c < cnt; c += kTauThreads) {
     const int e = e_lo + c;
@@ -214,139 +255,118 @@ __global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
     const Src o = source_of(d, K, pivot);
     float lo = INFINITY, hi = -INFINITY;
     if (o.w > 0.f) {
-      const float cc = (float)e + v * K.inv_dv;  // line centre, extended pixels
-      const float h = wk * o.b * K.inv_dv;       // half window, pixels
+      const float cc = __builtin_fmaf(v, K.inv_dv, (float)e);  // line centre, pixels
+      const float h = wk * o.b * K.inv_dv;                     // half window, pixels
       lo = cc - h;
       hi = cc + h;
     }
-    const float a = K.dv * o.r;  // step of t = d r per target pixel
-    rec[c] = make_float4(o.w, o.r, v, a);
-    qrec[c] = fexp2(-2.f * a * a);
-    // an unresolved line (b < 1.2 dv) makes the recurrence's dynamic range
-    // too wide for FP32: its group is evaluated with one exp per pair
-    int cold = (o.w > 0.f && a > kRecurrenceMaxStep) ? 1 : 0;
-    for (int m = 1; m < kGroup; m <<= 1) {
-      lo = fminf(lo, __shfl_xor(lo, m));
-      hi = fmaxf(hi, __shfl_xor(hi, m));
-      cold |= __shfl_xor(cold, m);
-    }
-    if ((threadIdx.x & (kGroup - 1)) == 0) {
-      bnd[c / kGroup] = make_float2(lo, hi);
-      gcold[c / kGroup] = cold;
-    }
+    rec[c] = make_float4(o.w, o.r, v, K.dv * o.r);
+    lo = stream_min<G>(lo);
+    hi = stream_max<G>(hi);
+    if ((threadIdx.x & (G - 1)) == 0) bnd[c / G] = make_float2(lo, hi);
   }
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  const int sl = lane % S;   // stream
-  const int ll = lane / S;   // lane within the stream
-  const int ngroups = cnt / kGroup;
+  const int sl = lane & (S - 1);  // stream
+  const int ll = lane / S;        // lane within the stream
+  const int ngroups = cnt / G;
   const float dv = K.dv;
 
   for (int qsub = 0; qsub < SUB; ++qsub) {
     const int t0 = i0 + (qsub * NW + wave) * Tt;
     if (t0 >= n) break;
+    // contiguous range of groups whose windows can reach [t0, t0 + Tt)
     const float tlo = (float)t0 - 1.f, thi = (float)(t0 + Tt) + 1.f;
-    bool hit0 = false, hit1 = false, cold0 = false, cold1 = false;
-    if (lane < ngroups) {
-      const float2 bb = bnd[lane];
-      hit0 = bb.y >= tlo && bb.x <= thi;
-      cold0 = gcold[lane] != 0;
+    int gfirst = NG, glast = -1;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int g = q * kWave + lane;
+      bool hit = false;
+      if (g < ngroups) {
+        const float2 bb = bnd[g];
+        hit = bb.y >= tlo && bb.x <= thi;
+      }
+      const uint64_t m = __ballot(hit);
+      if (m) {
+        gfirst = min(gfirst, q * kWave + (int)__builtin_ctzll(m));
+        glast = q * kWave + kWave - 1 - (int)__builtin_clzll(m);
+      }
     }
-    if (lane + kWave < ngroups) {
-      const float2 bb = bnd[lane + kWave];
-      hit1 = bb.y >= tlo && bb.x <= thi;
-      cold1 = gcold[lane + kWave] != 0;
-    }
-    const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
-    const uint64_t cm0 = __ballot(cold0), cm1 = __ballot(cold1);
     const int tb = t0 + ll * M;  // first target of this lane
-    float sum[M], comp[M], blk[M];
+    float acc[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) sum[k] = comp[k] = blk[k] = 0.f;
+    for (int k = 0; k < M; ++k) acc[k] = 0.f;
 
-    if (m0 | m1) {
-      const int gfirst = m0 ? __builtin_ctzll(m0) : kWave + __builtin_ctzll(m1);
-      const int glast = m1 ? 2 * kWave - 1 - __builtin_clzll(m1) : kWave - 1 - __builtin_clzll(m0);
-      float fd = (float)(tb - (e_lo + gfirst * kGroup + sl));  // target - source, exact
-      int since = 0;
-      for (int g = gfirst; g <= glast; ++g) {
-        const bool gc = ((g < kWave ? (cm0 >> g) : (cm1 >> (g - kWave))) & 1ull) != 0;
+    if (glast >= gfirst) {
+      float sum[M], comp[M];
 #pragma unroll
-        for (int u = 0; u < kGroup / S; ++u) {
-          const int c = g * kGroup + u * S + sl;
-          const float4 q = rec[c];
-          const float w = q.x, r = q.y, v = q.z;
-          if (DIRECT || gc) {
+      for (int k = 0; k < M; ++k) sum[k] = comp[k] = 0.f;
+      float fd = (float)(tb - (e_lo + gfirst * G + sl));  // target - source, exact
+      int c = gfirst * G + sl;
+      // one source of this stream against the lane's M targets
+      auto pair_step = [&](const float4 q) {
+        const float d0 = __builtin_fmaf(fd, dv, -q.z);
+        const float tt0 = d0 * q.y;
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-              const float d = __builtin_fmaf(fd + (float)k, dv, -v);
-              const float t = d * r;
-              blk[k] = __builtin_fmaf(w, fexp2(-(t * t)), blk[k]);
-            }
-          } else {
-            const float a = q.w, Q = qrec[c];
-            const float d0 = __builtin_fmaf(fd, dv, -v);
-            const float t0v = d0 * r;
-            float E = fexp2(-(t0v * t0v));
-            // With a <= 1 the clamp only acts where E_0 is already 0 in FP32 and
-            // the later terms are below 2^-85 of the line peak; it keeps
-            // 0 * inf out of the recurrence.
-            float Rk = fexp2(fminf(-(a * __builtin_fmaf(2.f, t0v, a)), 64.f));
-            blk[0] = __builtin_fmaf(w, E, blk[0]);
-#pragma unroll
-            for (int k = 1; k < M; ++k) {
-              E *= Rk;
-              blk[k] = __builtin_fmaf(w, E, blk[k]);
-              if (k + 1 < M) Rk *= Q;
-            }
-          }
-          fd -= (float)S;
+        for (int k = 0; k < M; ++k) {
+          const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, q.w, tt0);
+          acc[k] = __builtin_fmaf(q.x, fexp2(-(t * t)), acc[k]);
         }
-        if (++since == KB / (kGroup / S)) {
-          since = 0;
+        fd -= (float)G;
+      };
+      auto fold = [&]() {
 #pragma unroll
-          for (int k = 0; k < M; ++k) {
-            const float y = blk[k] - comp[k];
-            const float tt = sum[k] + y;
-            comp[k] = (tt - sum[k]) - y;
-            sum[k] = tt;
-            blk[k] = 0.f;
-          }
+        for (int k = 0; k < M; ++k) {
+          const float y = acc[k] - comp[k];
+          const float tt = sum[k] + y;
+          comp[k] = (tt - sum[k]) - y;
+          sum[k] = tt;
+          acc[k] = 0.f;
+        }
+      };
+      // two records in flight: the LDS read of the next source overlaps the
+      // arithmetic of the current one (rec is padded so the read past the
+      // last group stays inside the array)
+      float4 qa = rec[c];
+      int g = gfirst, since = 0;
+      for (; g + 1 <= glast; g += 2) {
+        const float4 qb = rec[c + G];
+        pair_step(qa);
+        qa = rec[c + 2 * G];
+        pair_step(qb);
+        c += 2 * G;
+        if (++since == KB / 2) {
+          since = 0;
+          fold();
         }
       }
+      if (g <= glast) pair_step(qa);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const float y = blk[k] - comp[k];
+        const float y = acc[k] - comp[k];
         const float tt = sum[k] + y;
         comp[k] = (tt - sum[k]) - y;
-        sum[k] = tt - comp[k];
-      }
-      // butterfly over the S streams that share these targets
-#pragma unroll
-      for (int m = 1; m < S; m <<= 1) {
-#pragma unroll
-        for (int k = 0; k < M; ++k) sum[k] += __shfl_xor(sum[k], m);
+        acc[k] = stream_sum<S>(tt - comp[k]);
       }
     }
-    if (sl == 0) {
+    // lanes sl = 0..M-1 of each stream group write one target each
+    if (sl < M) {
+      float v = acc[0];
 #pragma unroll
-      for (int k = 0; k < M; ++k)
-        if (tb + k < n) tau[off + tb + k] = sum[k];
+      for (int k = 1; k < M; ++k) v = (sl == k) ? acc[k] : v;
+      const int i = tb + sl;
+      if (i < n) tau[off + i] = v;
     }
   }
 }
 
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items, float *tau,
-                             bool direct, hipStream_t st) {
+                             hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  if (direct)
-    hipLaunchKernelGGL((tau_window_kernel<16, 4, true>), dim3((unsigned)n_items),
-                       dim3(kTauThreads), 0, st, b, items, tau);
-  else
-    hipLaunchKernelGGL((tau_window_kernel<16, 4, false>), dim3((unsigned)n_items),
-                       dim3(kTauThreads), 0, st, b, items, tau);
+  hipLaunchKernelGGL((tau_window_kernel<8, 4, kTauTile>), dim3((unsigned)n_items),
+                     dim3(kTauThreads), 0, st, b, items, tau);
   return hipGetLastError();
 }
 

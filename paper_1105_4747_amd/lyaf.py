@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "liblyaf.so")
 LYAF_OK, LYAF_EINVAL, LYAF_EDOMAIN, LYAF_ENOROOT = 0, -1, -2, -3
 LYAF_ENOCONV, LYAF_EDEVICE, LYAF_ENOMEM = -4, -5, -6
 STATUS_DOMAIN, STATUS_NOROOT, STATUS_NOCONV = 1, 2, 4
-FLAG_PLAIN, FLAG_PER_SKEWER, FLAG_DIRECT_EXP = 1, 2, 4
+FLAG_PLAIN, FLAG_PER_SKEWER = 1, 2
 
 EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_backward",
             "lyaf_tau_backward", "lyaf_status_read", "lyaf_strerror", "lyaf_version")

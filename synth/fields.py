@@ -115,7 +115,8 @@ def gaussian_skewers(rng: np.random.Generator, lengths):
 def lognormal_fields(g: np.ndarray, v: np.ndarray, sigma_lnD: float,
                      sigma_v: float = SIGMA_V):
     """Normalise (g, v) over the configuration and exponentiate g."""
-    g = g / g.std()
+    if g.std() > 0:  # a 1-pixel skewer has no k > 0 mode: uniform field
+        g = g / g.std()
     lnD = sigma_lnD * g - 0.5 * sigma_lnD ** 2
     D = np.exp(lnD)
     D /= D.mean()
