@@ -4,8 +4,9 @@
 One step = the whole path over the 4096 x 4096 workload (4096 skewers of 4096
 pixels, dv = 2 km/s, sigma_lnDelta = 1.2, T0 = 2e4 K, gamma = 1.3, window
 +-6 b, target <F> = 0.75; synthetic lognormal fields, seed 2) with the inputs
-resident in HBM: lyaf_tau (per-skewer reach pass + windowed tau kernel), then
-lyaf_normalise_mean_flux (FP64 root-find passes + tau' = A tau, F = exp(-tau')).
+resident in HBM: one replay of a tuned plan, i.e. the hipGraph of the reach
+pass, the windowed tau kernel (persistent launch), the FP64 mean-flux
+root-find passes and tau' = A tau, F = exp(-tau').
 
 Prints one JSON line.  ``value`` is skewer-pixels per second of tau + F.
 ``roofline`` describes the tau stage (the dominant kernel): algorithmic
@@ -61,6 +62,55 @@ def algorithmic_pairs(w) -> float:
     return total
 
 
+SHAPES = [(8, 4, 512), (8, 4, 256), (16, 4, 512), (8, 2, 512)]  # LYAF_FLAG_SHAPE(v)
+
+
+def batched_section(L, torch, dev, fields, timed, reps):
+    """The ragged 20,000-skewer batch (lengths 512-8192 px, dv 1-4 km/s, T0
+    and gamma drawn per skewer): one tuned plan (persistent launch in a
+    hipGraph) against the same windowed kernel launched once per skewer, and
+    the plain full-sum kernel on the first 200 skewers."""
+    w = fields.config3()
+    print(f"bench: batched {w.name}, P={w.n_pix}", file=sys.stderr, flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    delta, vpec, dvt, T0, gamma = t(w.delta), t(w.vpec), t(w.dv), t(w.T0), t(w.gamma)
+    P = w.n_pix
+    ts = torch.empty(P, device=dev, dtype=torch.float32)
+    F = torch.empty_like(ts)
+    A = torch.empty((), device=dev, dtype=torch.float64)
+    plan = L.Plan(delta, vpec, dvt, T0, gamma, w.offsets, w.target_F, ts, F, A,
+                  window_k=w.window_k, autotune=True)
+    info = plan.describe()
+    t_plan = timed(plan.execute, reps)
+    shape = [i for i, v in enumerate(SHAPES) if v == (info["streams"], info["targets_per_lane"],
+                                                      info["tile"])][0]
+    fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if info["persistent_grid"] > 0 else 0)
+    raw = torch.empty_like(ts)
+    tau = lambda flags: L.tau(delta, vpec, dvt, T0, gamma, w.offsets, raw,
+                              window_k=w.window_k, flags=flags)
+    t_tau = timed(lambda: tau(fl), reps)
+    t_grid = timed(lambda: tau(L.FLAG_SHAPE(shape)), reps)
+    t_per = timed(lambda: tau(L.FLAG_PER_SKEWER | L.FLAG_SHAPE(shape)), 1)
+    sub = w.subset(range(200))
+    d2 = [t(x) for x in (sub.delta, sub.vpec, sub.dv, sub.T0, sub.gamma)]
+    raw2 = torch.empty(sub.n_pix, device=dev, dtype=torch.float32)
+    t_plain = timed(lambda: L.tau(*d2, sub.offsets, raw2, window_k=w.window_k,
+                                  flags=L.FLAG_PLAIN), 1)
+    pairs = algorithmic_pairs(w)
+    ach = pairs * OPS_PER_PAIR / t_tau / 1e12
+    plan.close()
+    return {"workload": w.name, "n_pix": P, "plan": info,
+            "plan_step_ms": round(t_plan * 1e3, 4), "px_per_s": P / t_plan,
+            "tau_stage_ms": round(t_tau * 1e3, 4),
+            "tau_stage_one_launch_grid_ms": round(t_grid * 1e3, 4),
+            "tau_stage_launch_per_skewer_ms": round(t_per * 1e3, 3),
+            "plain_fp32_px_per_s_first200": sub.n_pix / t_plain,
+            "pairs_per_px": round(pairs / P, 3),
+            "tau_roofline": {"bound": "alu", "achieved": round(ach, 3),
+                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(ach / FP32_PEAK_TFLOPS, 4)}}
+
+
 def cpu_baseline(w, target_seconds=10.0):
     """FP64 oracle on the host: full sum of eq. (6) + mean-flux root-find, on
     the first skewers of the workload, sized to ~target_seconds of wall time."""
@@ -90,7 +140,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB float32 buffer 3 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; --gpus N > 1 is not "
@@ -107,85 +160,107 @@ def main():
         sys.exit(2)
     L.load()
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.ones(1 << 28, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_per_launch": 2 * src.numel() * 4}))
+        return
     w = getattr(fields, args.workload)()
     print(f"bench: workload {w.name}, P={w.n_pix}", file=sys.stderr, flush=True)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     delta, vpec, dvt, T0, gamma = t(w.delta), t(w.vpec), t(w.dv), t(w.T0), t(w.gamma)
     P = w.n_pix
-    raw = torch.empty(P, device=dev, dtype=torch.float32)
+    ts = torch.empty(P, device=dev, dtype=torch.float32)
     F = torch.empty(P, device=dev, dtype=torch.float32)
     A = torch.empty((), device=dev, dtype=torch.float64)
     stream = torch.cuda.current_stream()
 
-    def tau_stage(out):
-        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, out, tau_ref=w.tau_ref,
-              delta_pivot=w.delta_pivot, window_k=w.window_k)
-
-    def step():
-        tau_stage(raw)
-        L.normalise_mean_flux(raw, F, w.target_F, A)
+    # the whole forward (reach, windowed tau, mean-flux root-find, tau', F) as
+    # one tuned plan, replayed from a hipGraph
+    plan = L.Plan(delta, vpec, dvt, T0, gamma, w.offsets, w.target_F, ts, F, A,
+                  tau_ref=w.tau_ref, delta_pivot=w.delta_pivot, window_k=w.window_k,
+                  autotune=True)
+    info = plan.describe()
+    print(f"bench: plan {json.dumps(info)}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
-        step()
+        plan.execute()
     torch.cuda.synchronize()
-    if L.status_read() != 0:
+    if plan.status() != 0:
         raise RuntimeError("device status set during warmup")
 
     # timed region: exactly K steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        plan.execute()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = P * args.steps / elapsed
     print(f"bench: {ms_per_step:.4f} ms/step, {value:.4e} px/s", file=sys.stderr, flush=True)
 
-    # tau stage alone, HIP events on the launch stream
+    # the tau stage alone (reach + windowed kernel, the plan's shape and launch
+    # form), HIP events on the launch stream
+    shape = [i for i, v in enumerate(SHAPES) if v == (info["streams"], info["targets_per_lane"],
+                                                      info["tile"])][0]
+    tau_flags = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if info["persistent_grid"] > 0 else 0)
+    raw = torch.empty(P, device=dev, dtype=torch.float32)
+
+    def tau_stage(out, flags=tau_flags):
+        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, out, tau_ref=w.tau_ref,
+              delta_pivot=w.delta_pivot, window_k=w.window_k, flags=flags)
+
     reps = max(args.steps, 10)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        tau_stage(raw)
-    ev1.record(stream)
-    ev1.synchronize()
-    t_tau = ev0.elapsed_time(ev1) / reps * 1e-3
-    ev0.record(stream)
-    for _ in range(reps):
-        tmp = raw.clone()
-        L.normalise_mean_flux(tmp, F, w.target_F, A)
-    ev1.record(stream)
-    ev1.synchronize()
-    t_norm = ev0.elapsed_time(ev1) / reps * 1e-3
+
+    def timed(fn, n):
+        fn()
+        ev0.record(stream)
+        for _ in range(n):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / n * 1e-3
+
+    t_tau = timed(lambda: tau_stage(raw), reps)
+    tmp = torch.empty_like(raw)
+    t_copy = timed(lambda: tmp.copy_(raw), reps)
+    t_norm = timed(lambda: (tmp.copy_(raw), L.normalise_mean_flux(tmp, F, w.target_F, A)),
+                   reps) - t_copy
+    t_eager = timed(lambda: (tau_stage(raw, 0), L.normalise_mean_flux(raw, F, w.target_F, A)),
+                    reps)
     pairs = algorithmic_pairs(w)
     achieved = pairs * OPS_PER_PAIR / t_tau / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": None,
-                "kernel": "lyaf_tau (reach_kernel + tau_window_kernel)",
+                "kernel": "tau stage: reach_kernel + " + ("tau_window_persistent_kernel"
+                                                          if info["persistent_grid"] > 0
+                                                          else "tau_window_kernel"),
                 "kernel_ms": round(t_tau * 1e3, 4),
                 "pairs_per_launch": pairs, "pairs_per_px": round(pairs / P, 3),
                 "pair_rate_per_s": pairs / t_tau, "ops_per_pair": OPS_PER_PAIR}
-    extra = {"tau_stage_ms": round(t_tau * 1e3, 4),
-             "normalise_stage_ms_incl_copy": round(t_norm * 1e3, 4)}
+    extra = {"plan": info, "tau_stage_ms": round(t_tau * 1e3, 4),
+             "normalise_stage_ms": round(t_norm * 1e3, 4),
+             "eager_step_ms": round(t_eager * 1e3, 4)}
 
     if not args.no_plain:
         # the plain unbatched FP32 kernel (full O(N^2) sum, one launch per skewer)
         plain = torch.empty_like(raw)
-        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, plain, tau_ref=w.tau_ref,
-              delta_pivot=w.delta_pivot, window_k=w.window_k, flags=L.FLAG_PLAIN)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        L.tau(delta, vpec, dvt, T0, gamma, w.offsets, plain, tau_ref=w.tau_ref,
-              delta_pivot=w.delta_pivot, window_k=w.window_k, flags=L.FLAG_PLAIN)
-        ev1.record(stream)
-        ev1.synchronize()
-        t_plain = ev0.elapsed_time(ev1) * 1e-3
+        t_plain = timed(lambda: tau_stage(plain, L.FLAG_PLAIN), 1)
         extra["plain_fp32_tau_px_per_s"] = P / t_plain
         extra["plain_fp32_tau_ms"] = round(t_plain * 1e3, 3)
         extra["speedup_tau_vs_plain"] = round(t_plain / t_tau, 2)
         del plain
+
+    if not args.no_batched:
+        extra["batched"] = batched_section(L, torch, dev, fields, timed, reps)
+    plan.close()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -73,6 +73,14 @@ extern "C" {
 #define LYAF_FLAG_PLAIN 1u
 /* Launch the windowed kernel once per skewer instead of one batched launch. */
 #define LYAF_FLAG_PER_SKEWER 2u
+/* Persistent work-queue launch of the windowed kernel (see plans below). */
+#define LYAF_FLAG_PERSISTENT 4u
+/* Force windowed-kernel shape v (0 .. LYAF_NUM_SHAPES-1; the shapes a plan's
+ * tuner chooses from): flags |= LYAF_FLAG_SHAPE(v).  Shape 0 is the default:
+ * 8 source streams, 4 targets per lane, 512-pixel tiles; 1: 256-pixel tiles;
+ * 2: 16 streams; 3: 2 targets per lane. */
+#define LYAF_NUM_SHAPES 4
+#define LYAF_FLAG_SHAPE(v) ((((uint32_t)(v)) + 1u) << 8)
 
 typedef struct lyaf_skewers {
   int64_t n_skewers;      /* S >= 0 */
@@ -144,6 +152,51 @@ int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm,
                       const float *grad_tau_raw, float *grad_delta,
                       float *grad_vpec, double *grad_T0, double *grad_gamma,
                       void *stream);
+
+/* ---- plans: the whole forward, tuned and captured once, replayed many times ----
+ *
+ * Section 2.3 applies the same steps to every spectrum of a survey: eq. (6) per
+ * skewer, then one mean-flux rescale over all of them.  A plan binds one batch
+ * of skewers (their device arrays and host offsets), the parameters, the
+ * target mean flux and the output buffers, and records the whole forward
+ * (reach pass, windowed tau kernel, mean-flux root-find, tau' and F) as one
+ * hipGraph.  lyaf_plan_execute replays it: the array contents may change
+ * between executions, their addresses and the offsets may not.
+ *
+ * The windowed tau kernel runs as one persistent launch: a grid sized to the
+ * resident workgroups takes (skewer, tile) items from a device queue ordered by
+ * estimated cost (largest first), so ragged batches finish evenly.  With
+ * LYAF_PLAN_AUTOTUNE the kernel shape (source streams, targets per lane, tile
+ * length) and the launch form (persistent or one workgroup per item) are timed
+ * on the plan's own data at creation and the winner is cached in a text file
+ * ($LYAF_TUNE_CACHE, else $HOME/.cache/lyaf_tune.txt) under a key made of the
+ * device name, compute-unit count, batch shape buckets and window; later plans
+ * with the same key reuse it without timing.  Without the flag the default
+ * shape with the persistent launch is used.
+ *
+ * All plan memory is allocated in lyaf_plan_create; execution allocates
+ * nothing.  Creation runs kernels on `stream` (and synchronises it); the
+ * outputs then hold a valid result. */
+typedef struct lyaf_plan lyaf_plan;
+
+#define LYAF_PLAN_AUTOTUNE 1u  /* time the kernel shapes at creation (cached) */
+#define LYAF_PLAN_NO_GRAPH 2u  /* execute by re-enqueueing the kernels, no hipGraph */
+
+/* tau_out, F_out: DEVICE [P] float; A_dev: DEVICE double.  target_F in (0, 1).
+ * Errors: as lyaf_tau and lyaf_normalise_mean_flux, plus EDEVICE/ENOMEM from
+ * graph capture or allocation. */
+int lyaf_plan_create(const lyaf_skewers *sk, const lyaf_params *prm, double target_F,
+                     float *tau_out, float *F_out, double *A_dev, uint32_t plan_flags,
+                     void *stream, lyaf_plan **plan_out);
+/* Replay the forward on `stream` (any stream of the plan's device). */
+int lyaf_plan_execute(lyaf_plan *plan, void *stream);
+/* Read and clear the plan's status word (LYAF_STATUS_*); synchronises `stream`. */
+int lyaf_plan_status(lyaf_plan *plan, void *stream, uint32_t *device_status);
+/* NUL-terminated one-line description of the chosen configuration (JSON);
+ * returns the length it needs (excluding the NUL) or a negative code. */
+int lyaf_plan_describe(const lyaf_plan *plan, char *buf, int64_t buf_len);
+/* Free the plan (synchronises the device first).  NULL is accepted. */
+int lyaf_plan_destroy(lyaf_plan *plan);
 
 /* Read and clear the device status word of the current device's workspace
  * for `stream`.  Synchronises `stream`.  *device_status receives LYAF_STATUS_*

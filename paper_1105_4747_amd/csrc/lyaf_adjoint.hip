@@ -26,18 +26,15 @@ __device__ __forceinline__ float aexp2(float x) { return __builtin_amdgcn_exp2f(
 __device__ __forceinline__ float alog2(float x) { return __builtin_amdgcn_logf(x); }
 
 constexpr int kAdjThreads = 256;
-constexpr int kAdjTile = 256;  // sources per workgroup
+constexpr int kAdjTile = 256;  // sources per pass of the workgroup (one per thread)
+static_assert(kTauTile % kAdjTile == 0, "work items hold whole adjoint passes");
 
-__global__ __launch_bounds__(kAdjThreads) void tau_adjoint_kernel(
-    Batch b, const int2 *__restrict__ items, const float *__restrict__ g,
-    float *__restrict__ gdelta, float *__restrict__ gvpec, double *__restrict__ gpart) {
-  __shared__ float gl[kChunk];
-  __shared__ double shd[8];
-  const int2 item = items[blockIdx.x];
-  const int64_t s = item.x;
-  const int j0 = item.y * kAdjTile;
-  const SkewerConst K = b.skc[s];
-  const int64_t off = b.offsets[s];
+// One pass: sources j0 .. j0+255 of skewer s (one per thread).  Adds this
+// thread's Q_j and Q_j ln D_j to q_T0 and q_gam.
+__device__ void adjoint_pass(const Batch &b, const SkewerConst &K, int64_t off, int j0,
+                             const float *__restrict__ g, float *__restrict__ gdelta,
+                             float *__restrict__ gvpec, float *gl, double &q_T0,
+                             double &q_gam) {
   const int n = K.n;
   const int R = K.reach;
   const int j = j0 + (int)threadIdx.x;
@@ -63,6 +60,7 @@ __global__ __launch_bounds__(kAdjThreads) void tau_adjoint_kernel(
   const int e_lo = j0 - R;
   const int e_hi = j0 + kAdjTile + R;
   const int cnt = e_hi - e_lo;
+  __syncthreads();  // gl is reused across passes
   if (cnt <= n && cnt <= kChunk) {
     // windowed: targets e_lo .. e_hi-1 (extended, periodic)
     for (int c = threadIdx.x; c < cnt; c += kAdjThreads) {
@@ -126,7 +124,6 @@ __global__ __launch_bounds__(kAdjThreads) void tau_adjoint_kernel(
   }
 
   // per-source outputs (t = x sqrt(log2 e): x = t / sqrt(log2 e))
-  double q_T0 = 0.0, q_gam = 0.0;
   if (valid) {
     float gd = 0.f, gv = 0.f;
     if (w > 0.f) {
@@ -138,11 +135,28 @@ __global__ __launch_bounds__(kAdjThreads) void tau_adjoint_kernel(
       gv = 2.f * s1 / bj;
       const float below = (delta <= b.pivot) ? 1.f : 0.f;
       gd = (2.f * s0 + K.gm1 * below * Q) / delta;
-      q_T0 = (double)Q;
-      q_gam = (double)Q * ((double)l2D * kLn2);  // Q ln D
+      q_T0 += (double)Q;
+      q_gam += (double)Q * ((double)l2D * kLn2);  // Q ln D
     }
     gdelta[off + j] = gd;
     gvpec[off + j] = gv;
+  }
+}
+
+__global__ __launch_bounds__(kAdjThreads) void tau_adjoint_kernel(
+    Batch b, const int2 *__restrict__ items, const float *__restrict__ g,
+    float *__restrict__ gdelta, float *__restrict__ gvpec, double *__restrict__ gpart) {
+  __shared__ float gl[kChunk];
+  __shared__ double shd[8];
+  const int2 item = items[blockIdx.x];
+  const int64_t s = item.x;
+  const SkewerConst K = b.skc[s];
+  const int64_t off = b.offsets[s];
+  double q_T0 = 0.0, q_gam = 0.0;
+  for (int p = 0; p < kTauTile; p += kAdjTile) {
+    const int j0 = item.y * kTauTile + p;
+    if (j0 >= K.n) break;
+    adjoint_pass(b, K, off, j0, g, gdelta, gvpec, gl, q_T0, q_gam);
   }
   // FP64 workgroup sums of Q (for dL/dT0 after division by T0) and Q ln D
   double a0 = q_T0, a1 = q_gam;

@@ -1,11 +1,16 @@
 // lyaf_api.hip -- the C ABI declared in include/lyaf.h: host-side validation,
 // per-(device, stream) workspaces, work lists, and the kernel launches.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <numeric>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -19,6 +24,7 @@ std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 // Host mirrors of the work list currently uploaded to a workspace.
 struct HostPlan {
+  int tile = 0;                    // targets per work item of the uploaded list
   std::vector<int64_t> offsets;    // [S+1]
   std::vector<int64_t> item_base;  // [S+1]
   int64_t n_items = 0;
@@ -83,11 +89,11 @@ int get_ws(hipStream_t st, Workspace **out) {
   w->device = dev;
   w->stream = st;
   if ((e = hipMalloc((void **)&w->status, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMalloc((void **)&w->partials, sizeof(double) * 4 * kMaxPartialBlocks)) != hipSuccess ||
-      (e = hipMalloc((void **)&w->norm, sizeof(NormState))) != hipSuccess ||
+      (e = hipMalloc((void **)&w->partials, sizeof(double) * 8 * kMaxPartialBlocks)) != hipSuccess ||
+      (e = hipMalloc((void **)&w->norm, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
       (e = hipMalloc((void **)&w->ratio, sizeof(double))) != hipSuccess ||
       (e = hipMemset(w->status, 0, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMemset(w->norm, 0, sizeof(NormState))) != hipSuccess ||
+      (e = hipMemset(w->norm, 0, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
       (e = hipMemset(w->ratio, 0, sizeof(double))) != hipSuccess) {
     delete w;
     return map_err(e);
@@ -104,6 +110,9 @@ int check_args(const lyaf_skewers *sk, const lyaf_params *prm, int64_t *P_out) {
   if (!(prm->tau_ref > 0.0) || !isfinite(prm->tau_ref)) return LYAF_EINVAL;
   if (!(prm->delta_pivot > 0.0)) return LYAF_EINVAL;  // +INF allowed
   if (!(prm->window_k >= 0.0) || !isfinite(prm->window_k)) return LYAF_EINVAL;
+  if (((prm->flags >> 8) & 0xFu) > (uint32_t)kNumTauVariants) return LYAF_EINVAL;
+  if (prm->flags & ~(LYAF_FLAG_PLAIN | LYAF_FLAG_PER_SKEWER | LYAF_FLAG_PERSISTENT | 0xF00u))
+    return LYAF_EINVAL;
   const int64_t S = sk->n_skewers;
   int64_t P = 0;
   if (S > 0) {
@@ -124,22 +133,23 @@ int check_args(const lyaf_skewers *sk, const lyaf_params *prm, int64_t *P_out) {
 
 // Upload offsets, the (skewer, tile) work list and the per-skewer first item,
 // unless the workspace already holds this exact set of offsets.
-int ensure_plan(Workspace *ws, const lyaf_skewers *sk, HostPlan **out) {
+int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out) {
   HostPlan &hp = g_plans[ws];
   *out = &hp;
   const int64_t S = sk->n_skewers;
-  if ((int64_t)hp.offsets.size() == S + 1 &&
+  if (hp.tile == tile && (int64_t)hp.offsets.size() == S + 1 &&
       memcmp(hp.offsets.data(), sk->offsets, sizeof(int64_t) * (size_t)(S + 1)) == 0)
     return LYAF_OK;
   hipError_t e;
   // the pinned staging buffers may still feed an earlier copy on this stream
   if ((e = hipStreamSynchronize(ws->stream)) != hipSuccess) return map_err(e);
+  hp.tile = tile;
   hp.offsets.assign(sk->offsets, sk->offsets + S + 1);
   hp.item_base.assign((size_t)S + 1, 0);
   int64_t ni = 0;
   for (int64_t s = 0; s < S; ++s) {
     hp.item_base[s] = ni;
-    ni += (hp.offsets[s + 1] - hp.offsets[s] + kTauTile - 1) / kTauTile;
+    ni += (hp.offsets[s + 1] - hp.offsets[s] + tile - 1) / tile;
   }
   hp.item_base[S] = ni;
   hp.n_items = ni;
@@ -221,8 +231,10 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out, voi
   hipStream_t st = (hipStream_t)stream;
   Workspace *ws = nullptr;
   if ((rc = get_ws(st, &ws))) return rc;
+  const uint32_t shape = (prm->flags >> 8) & 0xFu;  // validated by check_args
+  const int variant = shape ? (int)shape - 1 : kTauVariantDefault;
   HostPlan *hp = nullptr;
-  if ((rc = ensure_plan(ws, sk, &hp))) return rc;
+  if ((rc = ensure_plan(ws, sk, kTauVariants[variant].tile, &hp))) return rc;
   const Batch b = make_batch(sk, prm, ws);
   hipError_t e = launch_reach(b, st);
   if (e != hipSuccess) return map_err(e);
@@ -233,9 +245,15 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out, voi
   } else if (prm->flags & LYAF_FLAG_PER_SKEWER) {
     for (int64_t s = 0; s < S && e == hipSuccess; ++s)
       e = launch_tau_window(b, ws->items + hp->item_base[s],
-                            hp->item_base[s + 1] - hp->item_base[s], tau_out, st);
+                            hp->item_base[s + 1] - hp->item_base[s], tau_out, st, variant);
+  } else if (prm->flags & LYAF_FLAG_PERSISTENT) {
+    if (!ws->queue && (e = hipMalloc((void **)&ws->queue, sizeof(unsigned int))) != hipSuccess)
+      return map_err(e);
+    const int pg = tau_persistent_grid(variant);
+    if (pg <= 0) return LYAF_EDEVICE;
+    e = launch_tau_window(b, ws->items, hp->n_items, tau_out, st, variant, pg, ws->queue);
   } else {
-    e = launch_tau_window(b, ws->items, hp->n_items, tau_out, st);
+    e = launch_tau_window(b, ws->items, hp->n_items, tau_out, st, variant);
   }
   return map_err(e);
 }
@@ -281,7 +299,7 @@ int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm, const floa
   Workspace *ws = nullptr;
   if ((rc = get_ws(st, &ws))) return rc;
   HostPlan *hp = nullptr;
-  if ((rc = ensure_plan(ws, sk, &hp))) return rc;
+  if ((rc = ensure_plan(ws, sk, kTauTile, &hp))) return rc;
   hipError_t e = grow_dev(ws->gpart, ws->gpart_cap, 2 * std::max<int64_t>(hp->n_items, 1));
   if (e != hipSuccess) return map_err(e);
   const Batch b = make_batch(sk, prm, ws);
@@ -313,6 +331,366 @@ int lyaf_status_read(void *stream, uint32_t *device_status) {
     return map_err(e);
   if ((e = hipMemset(ws->status, 0, sizeof(uint32_t))) != hipSuccess) return map_err(e);
   *device_status = v;
+  return LYAF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Plans.
+namespace lyaf {
+namespace {
+
+struct Candidate {
+  int variant;
+  int persistent;  // 1: persistent work-queue launch
+  double us;
+};
+
+std::string tune_cache_path() {
+  const char *p = getenv("LYAF_TUNE_CACHE");
+  if (p && *p) return p;
+  const char *h = getenv("HOME");
+  std::string dir = std::string(h && *h ? h : "/tmp") + "/.cache";
+  return dir + "/lyaf_tune.txt";
+}
+
+bool tune_cache_lookup(const std::string &key, Candidate *c) {
+  FILE *f = fopen(tune_cache_path().c_str(), "r");
+  if (!f) return false;
+  char k[512];
+  int v = 0, ps = 0;
+  double us = 0;
+  bool found = false;
+  while (fscanf(f, "%511s %d %d %lf", k, &v, &ps, &us) == 4) {
+    if (key == k && v >= 0 && v < kNumTauVariants && (ps == 0 || ps == 1)) {
+      c->variant = v;
+      c->persistent = ps;
+      c->us = us;
+      found = true;  // the last matching line wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_cache_store(const std::string &key, const Candidate &c) {
+  const std::string path = tune_cache_path();
+  const size_t slash = path.find_last_of('/');
+  if (slash != std::string::npos && slash > 0)
+    mkdir(path.substr(0, slash).c_str(), 0755);  // best effort, one level
+  FILE *f = fopen(path.c_str(), "a");
+  if (!f) return;  // an unwritable cache only costs a re-tune later
+  fprintf(f, "%s %d %d %.3f\n", key.c_str(), c.variant, c.persistent, c.us);
+  fclose(f);
+}
+
+}  // namespace
+}  // namespace lyaf
+
+struct lyaf_plan {
+  int device = -1;
+  lyaf_skewers sk{};
+  std::vector<int64_t> offsets;
+  lyaf_params prm{};
+  double target_F = 0.0;
+  float *tau_out = nullptr, *F_out = nullptr;
+  double *A_dev = nullptr;
+  uint32_t flags = 0;
+  int64_t P = 0;
+  lyaf::Workspace ws;
+  int2 *items = nullptr;
+  int64_t n_items = 0, items_cap = 0;
+  unsigned int *queue = nullptr;
+  int variant = lyaf::kTauVariantDefault;
+  int persistent_grid = 0;
+  bool tuned = false, from_cache = false;
+  std::string tune_key;
+  std::vector<lyaf::Candidate> timings;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<lyaf::SkewerConst> skc_host;
+};
+
+namespace lyaf {
+namespace {
+
+void plan_free(lyaf_plan *p) {
+  if (!p) return;
+  // teardown: errors here leave nothing further to release
+  (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  void *bufs[] = {p->items, p->queue, p->ws.status, p->ws.partials, p->ws.norm,
+                  p->ws.ratio, p->ws.skc, p->ws.offsets, p->ws.item_base};
+  for (void *q : bufs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+// (skewer, tile) work items for a tile length, largest estimated cost first.
+// A windowed tile of t targets stages t + 2R sources and evaluates about
+// t (t_sub + 2R) pairs; a full-sum tile evaluates t n.
+std::vector<int2> build_items(const lyaf_plan *p, int tile) {
+  const int64_t S = p->sk.n_skewers;
+  std::vector<int2> items;
+  std::vector<double> cost;
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t n = p->offsets[s + 1] - p->offsets[s];
+    const int R = p->skc_host.empty() ? 0 : p->skc_host[s].reach;
+    const int64_t nt = (n + tile - 1) / tile;
+    for (int64_t t = 0; t < nt; ++t) {
+      const double tg = (double)std::min<int64_t>(tile, n - t * tile);
+      const bool full = (int64_t)(32 + 2 * R + 24) > n;
+      items.push_back(make_int2((int)s, (int)t));
+      cost.push_back(full ? tg * (double)n : tg * (double)std::min<int64_t>(n, 64 + 2 * R));
+    }
+  }
+  std::vector<size_t> ord(items.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<int2> out(items.size());
+  for (size_t k = 0; k < ord.size(); ++k) out[k] = items[ord[k]];
+  return out;
+}
+
+hipError_t upload_items(lyaf_plan *p, const std::vector<int2> &items) {
+  hipError_t e = grow_dev(p->items, p->items_cap, (int64_t)std::max<size_t>(items.size(), 1));
+  if (e != hipSuccess) return e;
+  p->n_items = (int64_t)items.size();
+  if (items.empty()) return hipSuccess;
+  return hipMemcpy(p->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+}
+
+Batch plan_batch(lyaf_plan *p) { return make_batch(&p->sk, &p->prm, &p->ws); }
+
+hipError_t enqueue_tau(lyaf_plan *p, hipStream_t st) {
+  const Batch b = plan_batch(p);
+  hipError_t e = launch_reach(b, st);
+  if (e != hipSuccess) return e;
+  return launch_tau_window(b, p->items, p->n_items, p->tau_out, st, p->variant,
+                           p->persistent_grid, p->queue);
+}
+
+hipError_t enqueue_forward(lyaf_plan *p, hipStream_t st) {
+  hipError_t e = enqueue_tau(p, st);
+  if (e != hipSuccess) return e;
+  return launch_norm(p->P, p->tau_out, p->F_out, p->target_F, p->A_dev, p->ws, st);
+}
+
+std::string make_tune_key(const lyaf_plan *p) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return "v1|unknown";
+  const int64_t S = p->sk.n_skewers;
+  const double meanN = S > 0 ? (double)p->P / (double)S : 0.0;
+  int maxR = 0;
+  for (const auto &k : p->skc_host) maxR = std::max(maxR, k.reach);
+  char buf[512];
+  snprintf(buf, sizeof(buf), "v1|%s|cu%d|S2^%d|N2^%d|R2^%d|k%g", prop.gcnArchName,
+           prop.multiProcessorCount, (int)lround(log2((double)std::max<int64_t>(S, 1))),
+           (int)lround(log2(std::max(meanN, 1.0))), (int)lround(log2(std::max(maxR, 1))),
+           p->prm.window_k);
+  std::string k(buf);
+  for (auto &c : k)
+    if (c == ' ' || c == ':') c = '_';
+  return k;
+}
+
+// Time the tau stage of every candidate on the plan's data (3 replays after
+// one warm-up each) and keep the fastest.
+int autotune(lyaf_plan *p, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LYAF_EDEVICE;
+  Candidate best{-1, 0, 1e300};
+  for (int v = 0; v < kNumTauVariants; ++v) {
+    if (upload_items(p, build_items(p, kTauVariants[v].tile)) != hipSuccess) return LYAF_ENOMEM;
+    const int pg = tau_persistent_grid(v);
+    for (int ps = 0; ps < 2; ++ps) {
+      p->variant = v;
+      p->persistent_grid = ps ? pg : 0;
+      if (ps && pg <= 0) continue;
+      if (enqueue_tau(p, st) != hipSuccess) return LYAF_EDEVICE;
+      if (hipEventRecord(e0, st) != hipSuccess) return LYAF_EDEVICE;
+      for (int r = 0; r < 3; ++r)
+        if (enqueue_tau(p, st) != hipSuccess) return LYAF_EDEVICE;
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return LYAF_EDEVICE;
+      const Candidate c{v, ps, 1e3 * (double)ms / 3.0};
+      p->timings.push_back(c);
+      if (c.us < best.us) best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best.variant < 0) return LYAF_EDEVICE;
+  p->variant = best.variant;
+  p->persistent_grid = best.persistent ? tau_persistent_grid(best.variant) : 0;
+  tune_cache_store(p->tune_key, best);
+  return LYAF_OK;
+}
+
+}  // namespace
+}  // namespace lyaf
+
+extern "C" {
+
+int lyaf_plan_create(const lyaf_skewers *sk, const lyaf_params *prm, double target_F,
+                     float *tau_out, float *F_out, double *A_dev, uint32_t plan_flags,
+                     void *stream, lyaf_plan **plan_out) {
+  int64_t P = 0;
+  int rc = check_args(sk, prm, &P);
+  if (rc) return rc;
+  if (!plan_out || P <= 0 || !tau_out || !F_out || !A_dev) return LYAF_EINVAL;
+  if (!(target_F > 0.0 && target_F < 1.0) || F_out == tau_out) return LYAF_EINVAL;
+  if (plan_flags & ~(LYAF_PLAN_AUTOTUNE | LYAF_PLAN_NO_GRAPH)) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  lyaf_plan *p = new lyaf_plan();
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return map_err(e);
+  }
+  const int64_t S = sk->n_skewers;
+  p->sk = *sk;
+  p->offsets.assign(sk->offsets, sk->offsets + S + 1);
+  p->sk.offsets = p->offsets.data();
+  p->prm = *prm;
+  p->target_F = target_F;
+  p->tau_out = tau_out;
+  p->F_out = F_out;
+  p->A_dev = A_dev;
+  p->flags = plan_flags;
+  p->P = P;
+  if ((e = grow_dev(p->ws.offsets, p->ws.off_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(p->ws.skc, p->ws.skc_cap, S)) != hipSuccess ||
+      (e = hipMalloc((void **)&p->ws.status, sizeof(uint32_t))) != hipSuccess ||
+      (e = hipMalloc((void **)&p->ws.partials, sizeof(double) * 8 * kMaxPartialBlocks)) != hipSuccess ||
+      (e = hipMalloc((void **)&p->ws.norm, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
+      (e = hipMalloc((void **)&p->ws.ratio, sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void **)&p->queue, sizeof(unsigned int))) != hipSuccess ||
+      (e = hipMemset(p->ws.status, 0, sizeof(uint32_t))) != hipSuccess ||
+      (e = hipMemset(p->ws.norm, 0, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
+      (e = hipMemset(p->queue, 0, sizeof(unsigned int))) != hipSuccess ||
+      (e = hipMemcpy(p->ws.offsets, p->offsets.data(), sizeof(int64_t) * (S + 1),
+                     hipMemcpyHostToDevice)) != hipSuccess) {
+    plan_free(p);
+    return map_err(e);
+  }
+  // per-skewer reach of the data at hand: it orders the work list by cost
+  p->skc_host.resize((size_t)S);
+  if ((e = launch_reach(plan_batch(p), st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess ||
+      (S > 0 && (e = hipMemcpy(p->skc_host.data(), p->ws.skc, sizeof(SkewerConst) * S,
+                               hipMemcpyDeviceToHost)) != hipSuccess)) {
+    plan_free(p);
+    return map_err(e);
+  }
+  p->tune_key = make_tune_key(p);
+  Candidate cached{};
+  if (plan_flags & LYAF_PLAN_AUTOTUNE) {
+    p->tuned = true;
+    if (tune_cache_lookup(p->tune_key, &cached)) {
+      p->from_cache = true;
+      p->variant = cached.variant;
+      p->persistent_grid = cached.persistent ? tau_persistent_grid(cached.variant) : 0;
+      p->timings.push_back(cached);
+    } else if ((rc = autotune(p, st))) {
+      plan_free(p);
+      return rc;
+    }
+  } else {
+    p->variant = kTauVariantDefault;
+    p->persistent_grid = tau_persistent_grid(p->variant);
+  }
+  if ((e = upload_items(p, build_items(p, kTauVariants[p->variant].tile))) != hipSuccess) {
+    plan_free(p);
+    return map_err(e);
+  }
+  if (!(plan_flags & LYAF_PLAN_NO_GRAPH)) {
+    hipStream_t cap_st = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking)) != hipSuccess) {
+      plan_free(p);
+      return map_err(e);
+    }
+    e = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t el = enqueue_forward(p, cap_st);
+      e = hipStreamEndCapture(cap_st, &p->graph);
+      if (el != hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap_st);
+    if (e != hipSuccess) {
+      plan_free(p);
+      return map_err(e);
+    }
+  }
+  // one execution: the outputs are valid on return
+  e = p->exec ? hipGraphLaunch(p->exec, st) : enqueue_forward(p, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return map_err(e);
+  }
+  *plan_out = p;
+  return LYAF_OK;
+}
+
+int lyaf_plan_execute(lyaf_plan *plan, void *stream) {
+  if (!plan) return LYAF_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = plan->exec ? hipGraphLaunch(plan->exec, st) : enqueue_forward(plan, st);
+  return map_err(e);
+}
+
+int lyaf_plan_status(lyaf_plan *plan, void *stream, uint32_t *device_status) {
+  if (!plan || !device_status) return LYAF_EINVAL;
+  uint32_t v = 0;
+  hipError_t e;
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess ||
+      (e = hipMemcpy(&v, plan->ws.status, sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemset(plan->ws.status, 0, sizeof(uint32_t))) != hipSuccess)
+    return map_err(e);
+  *device_status = v;
+  return LYAF_OK;
+}
+
+int lyaf_plan_describe(const lyaf_plan *plan, char *buf, int64_t buf_len) {
+  if (!plan || (buf_len > 0 && !buf) || buf_len < 0) return LYAF_EINVAL;
+  const TauVariant &v = kTauVariants[plan->variant];
+  std::string t = "[";
+  for (size_t k = 0; k < plan->timings.size(); ++k) {
+    char c[128];
+    snprintf(c, sizeof(c), "%s{\"variant\":%d,\"persistent\":%d,\"us\":%.3f}", k ? "," : "",
+             plan->timings[k].variant, plan->timings[k].persistent, plan->timings[k].us);
+    t += c;
+  }
+  t += "]";
+  char head[768];
+  snprintf(head, sizeof(head),
+           "{\"streams\":%d,\"targets_per_lane\":%d,\"tile\":%d,\"persistent_grid\":%d,"
+           "\"items\":%lld,\"graph\":%s,\"tuned\":%s,\"from_cache\":%s,\"key\":\"%s\","
+           "\"timings_us\":",
+           v.S, v.M, v.tile, plan->persistent_grid, (long long)plan->n_items,
+           plan->exec ? "true" : "false", plan->tuned ? "true" : "false",
+           plan->from_cache ? "true" : "false", plan->tune_key.c_str());
+  std::string out = std::string(head) + t + "}";
+  if (buf_len > 0) {
+    const size_t n = std::min<size_t>(out.size(), (size_t)buf_len - 1);
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return (int)out.size();
+}
+
+int lyaf_plan_destroy(lyaf_plan *plan) {
+  if (!plan) return LYAF_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  plan_free(plan);
   return LYAF_OK;
 }
 

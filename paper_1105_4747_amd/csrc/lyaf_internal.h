@@ -29,8 +29,8 @@ constexpr float kTempExpR = -0.5f;  // d ln (1/b) / d ln T
 // Tiling of the windowed optical-depth kernel.
 constexpr int kWave = 64;
 constexpr int kTauThreads = 256;   // 4 waves per workgroup
-constexpr int kTauTile = 256;      // targets per workgroup (one work item)
-constexpr int kGroup = 16;         // sources per skip group
+constexpr int kTauTile = 512;      // targets per workgroup (one work item)
+constexpr int kGroup = 8;          // sources per window-bounds group (= source streams)
 constexpr int kChunk = 1536;       // sources staged in LDS at once
 
 // Per-skewer constants, computed in FP64 by the reach kernel and rounded once.
@@ -50,7 +50,7 @@ struct NormState {
   double A, lo, hi;
   double P, target;
   int32_t iter, done, status;
-  int32_t pad;
+  int32_t exact;  // 0: moments with FP32 exp2 (approach), 1: FP64 exp (final steps)
 };
 
 // Per-(device, stream) workspace.
@@ -58,8 +58,8 @@ struct Workspace {
   int device = -1;
   hipStream_t stream = nullptr;
   uint32_t *status = nullptr;       // sticky LYAF_STATUS_* bits
-  double *partials = nullptr;       // [kMaxPartialBlocks * 4]
-  NormState *norm = nullptr;
+  double *partials = nullptr;       // [2 * kMaxPartialBlocks * 4]
+  NormState *norm = nullptr;        // [kNormMaxIter + 2]
   double *ratio = nullptr;          // backward-normalise scalar
   // growable buffers
   SkewerConst *skc = nullptr;  int64_t skc_cap = 0;
@@ -67,9 +67,11 @@ struct Workspace {
   int2 *items = nullptr;       int64_t items_cap = 0;
   int64_t *item_base = nullptr; int64_t ib_cap = 0;    // [S+1] first item of each skewer
   double *gpart = nullptr;     int64_t gpart_cap = 0;  // adjoint per-item FP64 partials
+  unsigned int *queue = nullptr;                      // persistent work-queue counter
 };
-constexpr int kMaxPartialBlocks = 2048;
-constexpr int kNormMaxIter = 10;
+constexpr int kMaxPartialBlocks = 1024;
+constexpr int kNormMaxIter = 7;
+constexpr double kNormAcceptStep = 1e-5;
 
 // Kernel-side view of a skewer batch.
 struct Batch {
@@ -84,8 +86,22 @@ struct Batch {
 // ---------------------------------------------------------------------------
 // Launchers (return hipError_t of the launch).
 hipError_t launch_reach(const Batch &b, hipStream_t st);
+// Shapes of the windowed kernel that the tuner chooses from: S source streams
+// per wave, M targets per lane, TILE targets per work item.
+struct TauVariant {
+  int S, M, tile;
+};
+constexpr int kNumTauVariants = 4;
+constexpr int kTauVariantDefault = 0;
+extern const TauVariant kTauVariants[kNumTauVariants];
+
+// persistent_grid > 0 launches the persistent work-queue form with that many
+// workgroups (queue: a device counter, reset by a kernel inside the launch).
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items,
-                             float *tau, hipStream_t st);
+                             float *tau, hipStream_t st, int variant = kTauVariantDefault,
+                             int persistent_grid = 0, unsigned int *queue = nullptr);
+// Resident workgroups of the persistent form on the current device.
+int tau_persistent_grid(int variant);
 hipError_t launch_tau_plain(const Batch &b, int64_t skewer, int64_t n, float *tau,
                             hipStream_t st);
 hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F,

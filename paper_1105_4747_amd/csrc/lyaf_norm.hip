@@ -6,15 +6,15 @@
 // (norm_init) forms sum tau, the count of tau = 0 pixels and the domain check,
 // and starts from the Jensen lower bound A0 = -ln F / <tau> (g(A0) >= 0, and g
 // is convex and decreasing, so Newton steps from the left never overshoot).
-// Each further pass (norm_moments) evaluates S_k = sum tau^k exp(-A tau),
-// k = 0, 1, 2, in FP64 per workgroup; a one-workgroup kernel (norm_update)
-// sums the partials and applies a safeguarded Halley step (Newton, then
-// bisection, as fallbacks) inside the bracket.  A kernel boundary, not a
-// device-scope fence, publishes the partials: on a multi-XCD part a fence per
-// workgroup writes back and invalidates L2 and serialises the pass.  A fixed
-// number of passes is enqueued; once converged the remaining ones return at
-// once.  Partial sums are combined in a fixed order, so results are bitwise
-// reproducible.
+// Each further pass evaluates S_k = sum tau^k exp(-A tau), k = 0, 1, 2, in FP64
+// per workgroup.  The next pass (or the finalise kernel) begins with every
+// workgroup summing those partials in the same fixed order and taking the
+// same safeguarded Halley step (Newton, then bisection, as fallbacks) inside
+// the bracket.  A kernel boundary, not a device-scope fence, publishes the
+// partials: on a multi-XCD part a fence per workgroup writes back and
+// invalidates L2 and serialises the pass.  A fixed number of passes is
+// enqueued; once converged the remaining ones return at once.  Results are
+// bitwise reproducible.
 #include <math.h>
 
 #include "lyaf_internal.h"
@@ -47,6 +47,17 @@ __device__ __forceinline__ double exp_neg(double x) {
   p = fma(p, y, 1.0);
   p = fma(p, y, 1.0);
   return ldexp(p, -(int)k);
+}
+
+// exp(-x) for x >= 0 with FP64 argument reduction and the FP32 hardware
+// exp2 on the fraction: x log2 e = n + f, f in [0, 1), result 2^-n * 2^-f.
+// Relative error below 1e-7 (rounding f to FP32 and the exp2 unit); used for
+// the approach iterations only.
+__device__ __forceinline__ double exp_neg_fast(double y /* = x log2 e */) {
+  if (!(y <= 1074.0)) return 0.0;
+  const double nf = floor(y);
+  const float f = (float)(y - nf);
+  return ldexp((double)__builtin_amdgcn_exp2f(-f), -(int)nf);
 }
 
 template <int N>
@@ -83,96 +94,32 @@ __global__ __launch_bounds__(kNormThreads) void norm_init_kernel(const float *__
                                                                  int64_t P, double *partials) {
   __shared__ double sh[16];
   double v[3] = {0.0, 0.0, 0.0};  // sum tau, #zeros, #bad
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
-    const float t = tau[p];
+  auto add = [&](float t) {
     if (!(t >= 0.f) || !isfinite(t)) v[2] += 1.0;
     else {
       v[0] += (double)t;
       v[1] += (t == 0.f) ? 1.0 : 0.0;
     }
-  }
-  block_sum<3>(v, sh);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x * 4 + 0] = v[0];
-    partials[blockIdx.x * 4 + 1] = v[1];
-    partials[blockIdx.x * 4 + 2] = v[2];
-  }
-}
-
-// One workgroup: fixed-order sum of the init partials, starting state.
-__global__ __launch_bounds__(kNormThreads) void norm_start_kernel(int nblocks, int64_t P,
-                                                                  double target, NormState *st,
-                                                                  const double *partials,
-                                                                  uint32_t *status) {
-  __shared__ double sh[16];
-  double tot[3];
-  reduce_partials<3>(partials, nblocks, tot, sh);
-  if (threadIdx.x == 0) {
-    const double Pd = (double)P;
-    NormState s;
-    s.P = Pd;
-    s.target = target;
-    s.iter = 0;
-    s.done = 0;
-    s.status = 0;
-    s.pad = 0;
-    s.lo = 0.0;
-    s.hi = INFINITY;
-    s.A = -log(target) / (tot[0] / Pd);  // Jensen: g(A0) >= 0
-    if (tot[2] > 0.0) {
-      s.done = 1;
-      s.status = LYAF_STATUS_DOMAIN;
-    } else if (!(tot[1] / Pd < target)) {
-      s.done = 1;
-      s.status = LYAF_STATUS_NOROOT;
-    }
-    *st = s;
-    if (s.status) atomicOr(status, (uint32_t)s.status);
-  }
-}
-
-// One pass: S_k = sum tau^k exp(-A tau), k = 0..2, per workgroup.
-__global__ __launch_bounds__(kNormThreads) void norm_moments_kernel(const float *__restrict__ tau,
-                                                                    int64_t P, const NormState *st,
-                                                                    double *partials) {
-  __shared__ double sh[16];
-  if (st->done) return;  // converged (or failed) in an earlier pass
-  const double A = st->A;
-  double v[3] = {0.0, 0.0, 0.0};
+  };
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t done_to = 0;
   if ((reinterpret_cast<uintptr_t>(tau) & 15) == 0) {
     const int64_t P4 = P >> 2;
     const float4 *t4 = reinterpret_cast<const float4 *>(tau);
-    for (int64_t p = base; p < P4; p += stride) {
-      const float4 q = t4[p];
-      const double t[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double e = exp_neg(A * t[k]);
-        const double te = t[k] * e;
-        v[0] += e;
-        v[1] += te;
-        v[2] = fma(te, t[k], v[2]);
-      }
+    int64_t p = base;
+    for (; p + stride < P4; p += 2 * stride) {
+      const float4 qa = t4[p], qb = t4[p + stride];
+      add(qa.x); add(qa.y); add(qa.z); add(qa.w);
+      add(qb.x); add(qb.y); add(qb.z); add(qb.w);
     }
-    for (int64_t p = (P4 << 2) + base; p < P; p += stride) {
-      const double t = tau[p];
-      const double e = exp_neg(A * t);
-      v[0] += e;
-      v[1] += t * e;
-      v[2] = fma(t * e, t, v[2]);
+    for (; p < P4; p += stride) {
+      const float4 qa = t4[p];
+      add(qa.x); add(qa.y); add(qa.z); add(qa.w);
     }
-  } else {
-    for (int64_t p = base; p < P; p += stride) {
-      const double t = tau[p];
-      const double e = exp_neg(A * t);
-      v[0] += e;
-      v[1] += t * e;
-      v[2] = fma(t * e, t, v[2]);
-    }
+    done_to = P4 << 2;
   }
+  for (int64_t p = done_to + base; p < P; p += stride) add(tau[p]);
   block_sum<3>(v, sh);
   if (threadIdx.x == 0) {
     partials[blockIdx.x * 4 + 0] = v[0];
@@ -181,55 +128,171 @@ __global__ __launch_bounds__(kNormThreads) void norm_moments_kernel(const float 
   }
 }
 
-// One workgroup: fixed-order sum of the moment partials and one safeguarded
-// Halley step inside the bracket.
-__global__ __launch_bounds__(kNormThreads) void norm_update_kernel(int nblocks, NormState *st,
-                                                                   const double *partials,
-                                                                   uint32_t *status) {
-  __shared__ double sh[16];
-  if (st->done) return;
-  double tot[3];
-  reduce_partials<3>(partials, nblocks, tot, sh);
-  if (threadIdx.x == 0) {
-    NormState s = *st;
-    const double g = tot[0] / s.P - s.target;  // g(A) = <exp(-A tau)> - F
-    const double g1 = -tot[1] / s.P;           // g'(A)
-    const double g2 = tot[2] / s.P;            // g''(A)
-    double An = s.A;
-    bool conv = false;
-    if (g == 0.0) {
-      conv = true;
+// Starting state from the pass-0 sums: the Jensen lower bound
+// A0 = -ln F / <tau> (g(A0) >= 0), or a terminal state with a status bit.
+__device__ NormState norm_start(const double (&tot)[3], double P, double target) {
+  NormState s;
+  s.P = P;
+  s.target = target;
+  s.iter = 0;
+  s.done = 0;
+  s.status = 0;
+  s.exact = 0;
+  s.lo = 0.0;
+  s.hi = INFINITY;
+  s.A = -log(target) / (tot[0] / P);
+  if (tot[2] > 0.0) {
+    s.done = 1;
+    s.status = LYAF_STATUS_DOMAIN;
+  } else if (!(tot[1] / P < target)) {
+    s.done = 1;
+    s.status = LYAF_STATUS_NOROOT;
+  }
+  return s;
+}
+
+// One safeguarded Halley step from the moments S0, S1, S2 at s.A.
+__device__ NormState norm_step(NormState s, const double (&tot)[3]) {
+  const double g = tot[0] / s.P - s.target;  // g(A) = <exp(-A tau)> - F
+  const double g1 = -tot[1] / s.P;           // g'(A)
+  const double g2 = tot[2] / s.P;            // g''(A)
+  double An = s.A;
+  bool conv = false;
+  if (g == 0.0) {
+    conv = true;
+  } else {
+    if (g > 0.0) s.lo = s.A; else s.hi = s.A;
+    const double den = 2.0 * g1 * g1 - g * g2;
+    const double halley = (den != 0.0) ? s.A - 2.0 * g * g1 / den : NAN;
+    const double newton = (g1 < 0.0) ? s.A - g / g1 : NAN;
+    if (halley > s.lo && halley < s.hi) An = halley;
+    else if (newton > s.lo && newton < s.hi) An = newton;
+    else if (isfinite(s.hi)) An = 0.5 * (s.lo + s.hi);
+    else An = 2.0 * s.A;
+    // Halley converges cubically: once a step is below kNormAcceptStep of A
+    // the iterate it produces is within ~K 1e-15 of the root (K, the ratio of
+    // successive errors to the cube, is below 0.1 on lognormal-field tau),
+    // so it is accepted without another pass.
+    conv = fabs(An - s.A) <= kNormAcceptStep * An;
+  }
+  s.A = An;
+  s.iter += 1;
+  if (conv) {
+    // the approach used FP32 exponentials: finish with exact FP64 moments.
+    // Signs of g seen in the approach can be wrong within its ~1e-7 error,
+    // so the exact phase starts from an open bracket.
+    if (s.exact) {
+      s.done = 1;
     } else {
-      if (g > 0.0) s.lo = s.A; else s.hi = s.A;
-      const double den = 2.0 * g1 * g1 - g * g2;
-      const double halley = (den != 0.0) ? s.A - 2.0 * g * g1 / den : NAN;
-      const double newton = (g1 < 0.0) ? s.A - g / g1 : NAN;
-      if (halley > s.lo && halley < s.hi) An = halley;
-      else if (newton > s.lo && newton < s.hi) An = newton;
-      else if (isfinite(s.hi)) An = 0.5 * (s.lo + s.hi);
-      else An = 2.0 * s.A;
-      conv = fabs(An - s.A) <= 1e-12 * An;
+      s.exact = 1;
+      s.lo = 0.0;
+      s.hi = INFINITY;
     }
-    s.A = An;
-    s.iter += 1;
-    if (conv) {
-      s.done = 1;
-    } else if (s.iter >= kNormMaxIter) {
-      s.done = 1;
-      s.status = LYAF_STATUS_NOCONV;
-      atomicOr(status, (uint32_t)LYAF_STATUS_NOCONV);
+  }
+  return s;
+}
+
+// Pass k >= 1.  Every workgroup sums the previous pass's partials in the same
+// fixed order and takes the same step, so no update kernel and no
+// device-scope fence are needed; workgroup 0 records the state.  Then, unless
+// the iteration has finished, S_k = sum tau^k exp(-A tau), k = 0..2, at the
+// new A, per workgroup.
+__global__ __launch_bounds__(kNormThreads) void norm_pass_kernel(
+    int pass, const float *__restrict__ tau, int64_t P, double target,
+    const double *__restrict__ part_in, double *__restrict__ part_out,
+    const NormState *st_prev, NormState *st_out, uint32_t *status) {
+  __shared__ double sh[16];
+  __shared__ NormState shs;
+  if (threadIdx.x == 0) shs = (pass == 1) ? NormState{} : *st_prev;
+  __syncthreads();
+  if (pass > 1 && shs.done) {  // finished in an earlier pass
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st_out = shs;
+    return;
+  }
+  double tot[3];
+  reduce_partials<3>(part_in, gridDim.x, tot, sh);
+  if (threadIdx.x == 0) {
+    const NormState s = (pass == 1) ? norm_start(tot, (double)P, target) : norm_step(shs, tot);
+    shs = s;
+    if (blockIdx.x == 0) {
+      *st_out = s;
+      if (pass == 1 && s.status) atomicOr(status, (uint32_t)s.status);
     }
-    *st = s;
+  }
+  __syncthreads();
+  if (shs.done) return;
+  const double A = shs.A;
+  const double Al = shs.A * kLog2e;
+  const bool exact = shs.exact != 0;
+  double v[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
+  // two accumulator sets (elements alternate) halve the FP64 add chain
+  auto add2 = [&](double t, double (&a)[3]) {
+    const double e = exact ? exp_neg(A * t) : exp_neg_fast(Al * t);
+    const double te = t * e;
+    a[0] += e;
+    a[1] += te;
+    a[2] = fma(te, t, a[2]);
+  };
+  auto add = [&](double t) { add2(t, v); };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t done_to = 0;
+  if ((reinterpret_cast<uintptr_t>(tau) & 15) == 0) {
+    const int64_t P4 = P >> 2;
+    const float4 *t4 = reinterpret_cast<const float4 *>(tau);
+    int64_t p = base;
+    for (; p + stride < P4; p += 2 * stride) {  // two loads in flight
+      const float4 qa = t4[p], qb = t4[p + stride];
+      add2(qa.x, v); add2(qa.y, u); add2(qa.z, v); add2(qa.w, u);
+      add2(qb.x, v); add2(qb.y, u); add2(qb.z, v); add2(qb.w, u);
+    }
+    for (; p < P4; p += stride) {
+      const float4 qa = t4[p];
+      add2(qa.x, v); add2(qa.y, u); add2(qa.z, v); add2(qa.w, u);
+    }
+    done_to = P4 << 2;
+  }
+  for (int64_t p = done_to + base; p < P; p += stride) add((double)tau[p]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] += u[k];
+  block_sum<3>(v, sh);
+  if (threadIdx.x == 0) {
+    part_out[blockIdx.x * 4 + 0] = v[0];
+    part_out[blockIdx.x * 4 + 1] = v[1];
+    part_out[blockIdx.x * 4 + 2] = v[2];
   }
 }
 
-__global__ __launch_bounds__(kNormThreads) void norm_finalise_kernel(float *__restrict__ tau,
-                                                                     float *__restrict__ F,
-                                                                     int64_t P,
-                                                                     const NormState *st,
-                                                                     double *A_dev) {
-  const double A = st->A;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *A_dev = A;
+// Last step (from the last pass's moments unless already converged), then
+// tau' = A tau and F = exp(-tau').
+__global__ __launch_bounds__(kNormThreads) void norm_finalise_kernel(
+    float *__restrict__ tau, float *__restrict__ F, int64_t P, int nparts,
+    const double *__restrict__ part_in, const NormState *st_prev, NormState *st_out,
+    double *A_dev, uint32_t *status) {
+  __shared__ double sh[16];
+  __shared__ NormState shs;
+  if (threadIdx.x == 0) shs = *st_prev;
+  __syncthreads();
+  if (!shs.done) {  // one more step from the last pass's moments
+    double tot[3];
+    reduce_partials<3>(part_in, nparts, tot, sh);
+    if (threadIdx.x == 0) {
+      NormState s = norm_step(shs, tot);
+      // accepted if the step was small (then norm_step either finished or
+      // moved to the exact phase); otherwise the cap on passes was hit
+      const bool accepted = s.done || s.exact != shs.exact;
+      s.done = 1;
+      if (!accepted) s.status |= LYAF_STATUS_NOCONV;
+      shs = s;
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *st_out = shs;
+    *A_dev = shs.A;
+    if (shs.status & LYAF_STATUS_NOCONV) atomicOr(status, (uint32_t)LYAF_STATUS_NOCONV);
+  }
+  const double A = shs.A;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
     const float ts = (float)(A * (double)tau[p]);
@@ -239,7 +302,7 @@ __global__ __launch_bounds__(kNormThreads) void norm_finalise_kernel(float *__re
 }
 
 static int norm_grid(int64_t P) {
-  int64_t g = (P + kNormThreads * 8 - 1) / (kNormThreads * 8);
+  int64_t g = (P + kNormThreads * 16 - 1) / (kNormThreads * 16);
   if (g < 1) g = 1;
   if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
   return (int)g;
@@ -248,19 +311,17 @@ static int norm_grid(int64_t P) {
 hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F, double *A_dev,
                        Workspace &ws, hipStream_t st) {
   const int grid = norm_grid(n_pix);
+  double *part[2] = {ws.partials, ws.partials + 4 * kMaxPartialBlocks};
   hipLaunchKernelGGL(norm_init_kernel, dim3(grid), dim3(kNormThreads), 0, st, tau, n_pix,
-                     ws.partials);
-  hipLaunchKernelGGL(norm_start_kernel, dim3(1), dim3(kNormThreads), 0, st, grid, n_pix,
-                     target_F, ws.norm, ws.partials, ws.status);
-  for (int it = 0; it < kNormMaxIter; ++it) {
-    hipLaunchKernelGGL(norm_moments_kernel, dim3(grid), dim3(kNormThreads), 0, st, tau, n_pix,
-                       ws.norm, ws.partials);
-    hipLaunchKernelGGL(norm_update_kernel, dim3(1), dim3(kNormThreads), 0, st, grid, ws.norm,
-                       ws.partials, ws.status);
-  }
-  const int fgrid = (int)std::min<int64_t>((n_pix + 1023) / 1024 + 1, 65536);
-  hipLaunchKernelGGL(norm_finalise_kernel, dim3(fgrid), dim3(kNormThreads), 0, st, tau, F,
-                     n_pix, ws.norm, A_dev);
+                     part[0]);
+  for (int k = 1; k <= kNormMaxIter; ++k)
+    hipLaunchKernelGGL(norm_pass_kernel, dim3(grid), dim3(kNormThreads), 0, st, k, tau, n_pix,
+                       target_F, part[(k - 1) & 1], part[k & 1], ws.norm + (k - 1),
+                       ws.norm + k, ws.status);
+  const int fgrid = (int)std::min<int64_t>((n_pix + 2047) / 2048, 2048);
+  hipLaunchKernelGGL(norm_finalise_kernel, dim3(std::max(fgrid, 1)), dim3(kNormThreads), 0, st,
+                     tau, F, n_pix, grid, part[kNormMaxIter & 1], ws.norm + kNormMaxIter,
+                     ws.norm + kNormMaxIter + 1, A_dev, ws.status);
   return hipGetLastError();
 }
 

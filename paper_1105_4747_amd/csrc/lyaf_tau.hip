@@ -21,6 +21,8 @@
 //                       naive FP32 accumulation (the comparison baseline).
 #include <math.h>
 
+#include <algorithm>
+
 #include "lyaf_internal.h"
 
 namespace lyaf {
@@ -205,51 +207,51 @@ __device__ __forceinline__ float stream_max(float x) {
   return x;
 }
 
-// Windowed tile of TILE targets.  A wave is S source streams of 64/S lanes;
-// a lane owns M consecutive targets, so a wave sub-tile is (64/S)*M targets
-// and one loop iteration evaluates S sources (one skip group) against it.
-// Per source and lane: d0 = (i0 - j) dv - v_j exactly (one FMA on the integer
-// offset), t_k = d_k r_j = t_0 + k a_j (a_j = dv r_j), E_k = exp2(-t_k^2).
+// Windowed tile of kTauTile targets.  A wave is S source streams of L = 64/S
+// lanes; a lane owns M consecutive targets, so the streams of a wave share a
+// sub-tile of L*M targets and one loop iteration evaluates S sources (one
+// bounds group) against it.  The wave visits only the contiguous run of groups
+// whose windows reach the sub-tile, then the streams' partial sums meet in a
+// DPP butterfly.  Per source and lane: d0 = (i - j) dv - v_j exactly (one FMA
+// on the integer offset), t_k = t_0 + k a_j (a_j = dv r_j),
+// E_k = exp2(-t_k^2), acc_k += w_j E_k.
 template <int S, int M, int TILE>
-__global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
-                                                                 const int2 *__restrict__ items,
-                                                                 float *__restrict__ tau) {
-  constexpr int G = S;                   // sources per skip group = streams
+__device__ __forceinline__ void tau_tile(const Batch &b, const int2 item, float *__restrict__ tau,
+                                         float4 *rec, float2 *bnd) {
+  constexpr int G = S;                   // sources per bounds group = streams
   constexpr int L = kWave / S;           // lanes per stream
   constexpr int Tt = L * M;              // targets per wave sub-tile
   constexpr int NW = kTauThreads / kWave;
   constexpr int SUB = TILE / (NW * Tt);
-  constexpr int NG = kChunk / G;         // groups that fit in LDS
-  constexpr int NB = (NG + kWave - 1) / kWave;
+  constexpr int NG = kChunk / G;
   static_assert(SUB * NW * Tt == TILE, "tile shape");
-  constexpr int KB = 16;                 // Kahan fold period (iterations)
+  constexpr int KB = 16;                 // Kahan fold period (sources per stream)
 
-  __shared__ float4 rec[kChunk + 2 * G];
-  __shared__ float2 bnd[NG];
-
-  const int2 item = items[blockIdx.x];
   const int64_t s = item.x;
   const int i0 = item.y * TILE;
   const SkewerConst K = b.skc[s];
   const int64_t off = b.offsets[s];
   const int n = K.n;
   const int R = K.reach;
+  const int i_end = min(i0 + TILE, n);
 
+  // staged sources: extended (periodic) indices e_lo .. e_hi-1.  A short
+  // skewer appears together with its images; every sub-tile's run of sources
+  // stays shorter than the skewer, so no source is counted twice.
   int e_lo = i0 - R;
   e_lo = (e_lo >= 0) ? (e_lo / G) * G : -(((-e_lo) + G - 1) / G) * G;
-  int e_hi = i0 + TILE + R;
+  int e_hi = i_end + R;
   e_hi = ((e_hi + G - 1) / G) * G;
   const int cnt = e_hi - e_lo;
-  if (cnt > n || cnt > kChunk) {  // the window covers the box: full sum
-    for (int q = 0; q < TILE; q += kTauThreads)
-      full_sum_tile<true>(b, K, off, i0 + q, tau, rec);
+  if (Tt + 2 * R + 3 * G > n || cnt > kChunk) {  // the window covers the box
+    for (int q = i0; q < i_end; q += kTauThreads)
+      full_sum_tile<true>(b, K, off, q, tau, rec);
     return;
   }
 
-  // ---- stage sources e_lo .. e_hi-1 (extended, periodic) and group bounds
   const float pivot = b.pivot, wk = b.window_k;
   for (int c = threadIdx.x; c < cnt; c += kTauThreads) {
-    const int e = e_lo + c;
+    const int e = e_lo + c;  // -n < e < 2n in window mode (R < n/2)
     const int j = e < 0 ? e + n : (e >= n ? e - n : e);
     const float d = b.delta[off + j], v = b.vpec[off + j];
     const Src o = source_of(d, K, pivot);
@@ -268,32 +270,38 @@ __global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  // wave-uniform values live in scalar registers: the sub-tile loop and the
+  // group scan then need no execution-mask bookkeeping
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int sl = lane & (S - 1);  // stream
   const int ll = lane / S;        // lane within the stream
   const int ngroups = cnt / G;
   const float dv = K.dv;
 
   for (int qsub = 0; qsub < SUB; ++qsub) {
-    const int t0 = i0 + (qsub * NW + wave) * Tt;
-    if (t0 >= n) break;
-    // contiguous range of groups whose windows can reach [t0, t0 + Tt)
+    const int t0 = __builtin_amdgcn_readfirstlane(i0 + (qsub * NW + wave) * Tt);
+    if (t0 >= i_end) break;
+    // contiguous run of groups whose windows reach [t0, t0 + Tt): only groups
+    // within the reach of the sub-tile can, so one ballot usually covers them
     const float tlo = (float)t0 - 1.f, thi = (float)(t0 + Tt) + 1.f;
+    const int gs = max(0, (t0 - R - e_lo) / G - 1);
+    const int ge = min(ngroups - 1, (t0 + Tt + R - e_lo) / G + 1);
     int gfirst = NG, glast = -1;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int g = q * kWave + lane;
+    for (int gb = gs; gb <= ge; gb += kWave) {
+      const int g = gb + lane;
       bool hit = false;
-      if (g < ngroups) {
+      if (g <= ge) {
         const float2 bb = bnd[g];
         hit = bb.y >= tlo && bb.x <= thi;
       }
       const uint64_t m = __ballot(hit);
       if (m) {
-        gfirst = min(gfirst, q * kWave + (int)__builtin_ctzll(m));
-        glast = q * kWave + kWave - 1 - (int)__builtin_clzll(m);
+        gfirst = min(gfirst, gb + (int)__builtin_ctzll(m));
+        glast = gb + kWave - 1 - (int)__builtin_clzll(m);
       }
     }
+    gfirst = __builtin_amdgcn_readfirstlane(gfirst);
+    glast = __builtin_amdgcn_readfirstlane(glast);
     const int tb = t0 + ll * M;  // first target of this lane
     float acc[M];
 #pragma unroll
@@ -343,31 +351,114 @@ __global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
         }
       }
       if (g <= glast) pair_step(qa);
+      fold();
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const float y = acc[k] - comp[k];
-        const float tt = sum[k] + y;
-        comp[k] = (tt - sum[k]) - y;
-        acc[k] = stream_sum<S>(tt - comp[k]);
-      }
+      for (int k = 0; k < M; ++k) acc[k] = stream_sum<S>(sum[k] - comp[k]);
     }
     // lanes sl = 0..M-1 of each stream group write one target each
     if (sl < M) {
-      float v = acc[0];
+      float o = acc[0];
 #pragma unroll
-      for (int k = 1; k < M; ++k) v = (sl == k) ? acc[k] : v;
+      for (int k = 1; k < M; ++k) o = (sl == k) ? acc[k] : o;
       const int i = tb + sl;
-      if (i < n) tau[off + i] = v;
+      if (i < i_end) tau[off + i] = o;
     }
   }
 }
 
+// One work item (skewer, tile) per workgroup.
+template <int S, int M, int TILE>
+__global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
+                                                                 const int2 *__restrict__ items,
+                                                                 float *__restrict__ tau) {
+  __shared__ float4 rec[kChunk + 2 * S];
+  __shared__ float2 bnd[kChunk / S];
+  tau_tile<S, M, TILE>(b, items[blockIdx.x], tau, rec, bnd);
+}
+
+// Persistent form: a grid sized to the resident workgroups takes items from a
+// queue (the work list is sorted by estimated cost, largest first) until it is
+// empty; every workgroup leaves the loop once the counter passes n_items.
+template <int S, int M, int TILE>
+__global__ __launch_bounds__(kTauThreads) void tau_window_persistent_kernel(
+    Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
+    float *__restrict__ tau) {
+  __shared__ float4 rec[kChunk + 2 * S];
+  __shared__ float2 bnd[kChunk / S];
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS and `next`
+    if (threadIdx.x == 0) next = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int idx = next;
+    if (idx >= n_items) break;
+    tau_tile<S, M, TILE>(b, items[idx], tau, rec, bnd);
+  }
+}
+
+__global__ void reset_queue_kernel(unsigned int *queue) { *queue = 0u; }
+
+namespace {
+struct VariantFns {
+  const void *grid_fn;
+  const void *pers_fn;
+  void (*grid)(const Batch &, const int2 *, int64_t, float *, hipStream_t);
+  void (*pers)(const Batch &, const int2 *, int64_t, unsigned int *, int, float *, hipStream_t);
+};
+
+template <int S, int M, int TILE>
+VariantFns make_variant() {
+  VariantFns v;
+  v.grid_fn = reinterpret_cast<const void *>(&tau_window_kernel<S, M, TILE>);
+  v.pers_fn = reinterpret_cast<const void *>(&tau_window_persistent_kernel<S, M, TILE>);
+  v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
+    hipLaunchKernelGGL((tau_window_kernel<S, M, TILE>), dim3((unsigned)n), dim3(kTauThreads), 0,
+                       st, b, items, tau);
+  };
+  v.pers = [](const Batch &b, const int2 *items, int64_t n, unsigned int *queue, int grid,
+              float *tau, hipStream_t st) {
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, queue);
+    hipLaunchKernelGGL((tau_window_persistent_kernel<S, M, TILE>), dim3((unsigned)grid),
+                       dim3(kTauThreads), 0, st, b, items, (int)n, queue, tau);
+  };
+  return v;
+}
+
+const VariantFns &variant_fns(int v) {
+  static const VariantFns table[kNumTauVariants] = {
+      make_variant<8, 4, 512>(),   // kTauVariantDefault
+      make_variant<8, 4, 256>(),
+      make_variant<16, 4, 512>(),
+      make_variant<8, 2, 512>(),
+  };
+  return table[v];
+}
+}  // namespace
+
+const TauVariant kTauVariants[kNumTauVariants] = {
+    {8, 4, 512}, {8, 4, 256}, {16, 4, 512}, {8, 2, 512}};
+
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items, float *tau,
-                             hipStream_t st) {
+                             hipStream_t st, int variant, int persistent_grid,
+                             unsigned int *queue) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL((tau_window_kernel<8, 4, kTauTile>), dim3((unsigned)n_items),
-                     dim3(kTauThreads), 0, st, b, items, tau);
+  const VariantFns &f = variant_fns(variant);
+  if (persistent_grid > 0)
+    f.pers(b, items, n_items, queue, persistent_grid, tau, st);
+  else
+    f.grid(b, items, n_items, tau, st);
   return hipGetLastError();
+}
+
+int tau_persistent_grid(int variant) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, variant_fns(variant).pers_fn,
+                                                   kTauThreads, 0) != hipSuccess)
+    return 0;
+  return std::max(1, cus * per_cu);
 }
 
 // ---------------------------------------------------------------------------

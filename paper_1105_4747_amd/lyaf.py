@@ -27,10 +27,20 @@ LIB_PATH = os.path.join(HERE, "liblyaf.so")
 LYAF_OK, LYAF_EINVAL, LYAF_EDOMAIN, LYAF_ENOROOT = 0, -1, -2, -3
 LYAF_ENOCONV, LYAF_EDEVICE, LYAF_ENOMEM = -4, -5, -6
 STATUS_DOMAIN, STATUS_NOROOT, STATUS_NOCONV = 1, 2, 4
-FLAG_PLAIN, FLAG_PER_SKEWER = 1, 2
+FLAG_PLAIN, FLAG_PER_SKEWER, FLAG_PERSISTENT = 1, 2, 4
+NUM_SHAPES = 4
+PLAN_AUTOTUNE, PLAN_NO_GRAPH = 1, 2
+
+
+def FLAG_SHAPE(v: int) -> int:
+    """Force windowed-kernel shape v (LYAF_FLAG_SHAPE)."""
+    return (int(v) + 1) << 8
+
 
 EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_backward",
-            "lyaf_tau_backward", "lyaf_status_read", "lyaf_strerror", "lyaf_version")
+            "lyaf_tau_backward", "lyaf_status_read", "lyaf_strerror", "lyaf_version",
+            "lyaf_plan_create", "lyaf_plan_execute", "lyaf_plan_status", "lyaf_plan_describe",
+            "lyaf_plan_destroy")
 
 
 class LyafError(RuntimeError):
@@ -87,6 +97,17 @@ def load():
         lib.lyaf_strerror.restype = ctypes.c_char_p
         lib.lyaf_version.argtypes = []
         lib.lyaf_version.restype = i32
+        lib.lyaf_plan_create.argtypes = [PS, PP, dbl, vp, vp, vp, ctypes.c_uint32, vp,
+                                         ctypes.POINTER(vp)]
+        lib.lyaf_plan_create.restype = i32
+        lib.lyaf_plan_execute.argtypes = [vp, vp]
+        lib.lyaf_plan_execute.restype = i32
+        lib.lyaf_plan_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
+        lib.lyaf_plan_status.restype = i32
+        lib.lyaf_plan_describe.argtypes = [vp, ctypes.c_char_p, i64]
+        lib.lyaf_plan_describe.restype = i32
+        lib.lyaf_plan_destroy.argtypes = [vp]
+        lib.lyaf_plan_destroy.restype = i32
         _lib = lib
         return lib
 
@@ -178,6 +199,57 @@ def status_read(stream=None) -> int:
 
 def version() -> int:
     return int(load().lyaf_version())
+
+
+class Plan:
+    """lyaf_plan_*: the whole forward (tau, mean-flux rescale, F) bound to
+    fixed device buffers, captured once as a hipGraph and replayed.
+
+    ``tau_out`` receives tau' = A tau, ``F_out`` receives F, ``A_out`` (a
+    float64 device scalar) receives A.  The tensors passed here must stay
+    alive (and at the same address) for the life of the plan."""
+
+    def __init__(self, delta, vpec, dv, T0, gamma, offsets, target_F, tau_out, F_out, A_out,
+                 tau_ref=1.0, delta_pivot=10.0, window_k=6.0, autotune=False, graph=True,
+                 stream=None):
+        sk, off = make_skewers(delta, vpec, dv, T0, gamma, offsets)
+        prm = make_params(tau_ref, delta_pivot, window_k, 0)
+        flags = (PLAN_AUTOTUNE if autotune else 0) | (0 if graph else PLAN_NO_GRAPH)
+        h = ctypes.c_void_p()
+        self._keep = (delta, vpec, dv, T0, gamma, tau_out, F_out, A_out, off)
+        _check(load().lyaf_plan_create(ctypes.byref(sk), ctypes.byref(prm), float(target_F),
+                                       _ptr(tau_out), _ptr(F_out), _ptr(A_out), flags,
+                                       _stream(stream), ctypes.byref(h)), "lyaf_plan_create")
+        self._h = h
+
+    def execute(self, stream=None):
+        _check(load().lyaf_plan_execute(self._h, _stream(stream)), "lyaf_plan_execute")
+
+    def status(self, stream=None) -> int:
+        v = ctypes.c_uint32(0)
+        _check(load().lyaf_plan_status(self._h, _stream(stream), ctypes.byref(v)),
+               "lyaf_plan_status")
+        return int(v.value)
+
+    def describe(self) -> dict:
+        import json
+        n = load().lyaf_plan_describe(self._h, None, 0)
+        if n < 0:
+            _check(n, "lyaf_plan_describe")
+        buf = ctypes.create_string_buffer(n + 1)
+        load().lyaf_plan_describe(self._h, buf, n + 1)
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lyaf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -91,7 +91,7 @@ def gaussian_skewers(rng: np.random.Generator, lengths):
     g = np.empty(P)
     v = np.empty(P)
     uniq = np.unique(lengths)
-    if len(uniq) == 1 and len(lengths) > 0:
+    if len(uniq) == 1 and len(lengths) > 0 and uniq[0] > 0:
         n = int(uniq[0])
         z = rng.standard_normal((len(lengths), n))
         amp, vf = _spectral_filters(n)
@@ -99,10 +99,12 @@ def gaussian_skewers(rng: np.random.Generator, lengths):
         g[:] = np.fft.irfft(zk, n=n, axis=1).ravel()
         v[:] = np.fft.irfft(zk * vf, n=n, axis=1).ravel()
         return g, v
-    filt = {int(n): _spectral_filters(int(n)) for n in uniq}
+    filt = {int(n): _spectral_filters(int(n)) for n in uniq if n > 0}
     pos = 0
     for n in lengths:
         n = int(n)
+        if n == 0:  # an empty skewer draws nothing
+            continue
         z = rng.standard_normal(n)
         amp, vf = filt[n]
         zk = np.fft.rfft(z) * amp
@@ -115,6 +117,8 @@ def gaussian_skewers(rng: np.random.Generator, lengths):
 def lognormal_fields(g: np.ndarray, v: np.ndarray, sigma_lnD: float,
                      sigma_v: float = SIGMA_V):
     """Normalise (g, v) over the configuration and exponentiate g."""
+    if g.size == 0:
+        return np.zeros(0, np.float32), np.zeros(0, np.float32)
     if g.std() > 0:  # a 1-pixel skewer has no k > 0 mode: uniform field
         g = g / g.std()
     lnD = sigma_lnD * g - 0.5 * sigma_lnD ** 2

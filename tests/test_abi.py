@@ -113,6 +113,30 @@ def test_tau_backward_rejects_bad_arguments(lib):
     assert lib.lyaf_status_read(None, None) == L.LYAF_EINVAL
 
 
+def test_plan_create_rejects_bad_arguments(lib):
+    off = np.array([0, 10], np.int64)
+    d = ctypes.c_void_p(0x1000)
+    sk = L.Skewers(1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), d, d, d, d, d)
+    prm = L.Params(1.0, 10.0, 6.0, 0)
+    h = ctypes.c_void_p()
+    f = lib.lyaf_plan_create
+    o, F, A = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000)
+    assert f(ctypes.byref(sk), ctypes.byref(prm), 0.8, o, F, A, 0, None, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(sk), ctypes.byref(prm), 1.2, o, F, A, 0, None,
+             ctypes.byref(h)) == L.LYAF_EINVAL
+    assert f(ctypes.byref(sk), ctypes.byref(prm), 0.8, o, o, A, 0, None,
+             ctypes.byref(h)) == L.LYAF_EINVAL
+    assert f(ctypes.byref(sk), ctypes.byref(prm), 0.8, o, F, None, 0, None,
+             ctypes.byref(h)) == L.LYAF_EINVAL
+    assert f(ctypes.byref(sk), ctypes.byref(prm), 0.8, o, F, A, 64, None,
+             ctypes.byref(h)) == L.LYAF_EINVAL
+    assert lib.lyaf_plan_execute(None, None) == L.LYAF_EINVAL
+    assert lib.lyaf_plan_destroy(None) == L.LYAF_OK
+    assert lib.lyaf_plan_describe(None, None, 0) == L.LYAF_EINVAL
+    bad = L.Params(1.0, 10.0, 6.0, L.FLAG_SHAPE(L.NUM_SHAPES))
+    assert lib.lyaf_tau(ctypes.byref(sk), ctypes.byref(bad), o, None) == L.LYAF_EINVAL
+
+
 def test_library_does_not_link_the_oracle():
     """The product library and its binding reference nothing under oracle/."""
     pkg = os.path.join(ROOT, "paper_1105_4747_amd")

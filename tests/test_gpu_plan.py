@@ -1,0 +1,140 @@
+"""GPU tests of the batched forms: every windowed-kernel shape and launch form
+against the oracle, plans (hipGraph capture of the whole forward) against the
+eager calls, replay determinism with other work in between and with inputs
+changed in place, and the autotuner's cache."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import (OnDevice, assert_F_close, assert_tau_close, gpu_normalise, gpu_tau, to_dev,
+                      A_REL)
+from oracle import oracle as O
+from synth import fields
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_tau(w):
+    return O.tau(w.delta, w.vpec, w.dv, w.T0, w.gamma, offsets=w.offsets, tau_ref=w.tau_ref,
+                 delta_pivot=w.delta_pivot)
+
+
+def ragged_mix(seed=41, S=24):
+    """Ragged batch: short skewers (full-sum path and halo-duplicated staging),
+    long ones, dv from 1 to 4 km/s."""
+    return fields.ragged_workload("mix", S, 40, 3000, 1.0, 4.0, 1e4, 2.5e4, 1.1, 1.6, 1.0, 0.8,
+                                  6.0, seed=seed)
+
+
+@pytest.mark.parametrize("shape", range(4))
+@pytest.mark.parametrize("persistent", [False, True])
+def test_every_shape_and_launch_form(shape, persistent):
+    from paper_1105_4747_amd import lyaf as L
+    fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if persistent else 0)
+    for w in (fields.config1().subset(range(16)), ragged_mix()):
+        print(f"case: {w.name} shape={shape} persistent={persistent}", flush=True)
+        got = gpu_tau(w, flags=fl).cpu().numpy()
+        assert_tau_close(got, oracle_tau(w), f"{w.name} shape {shape}")
+
+
+def _plan(w, d, autotune=False, graph=True):
+    import torch
+    from paper_1105_4747_amd import lyaf as L
+    ts = torch.empty(w.n_pix, device="cuda:0", dtype=torch.float32)
+    F = torch.empty_like(ts)
+    A = torch.empty((), device="cuda:0", dtype=torch.float64)
+    p = L.Plan(d.delta, d.vpec, d.dv, d.T0, d.gamma, d.offsets, w.target_F, ts, F, A,
+               tau_ref=w.tau_ref, delta_pivot=w.delta_pivot, window_k=w.window_k,
+               autotune=autotune, graph=graph)
+    return p, ts, F, A
+
+
+def _eager(w, d):
+    raw = gpu_tau(w, d=d)
+    return gpu_normalise(raw, w.target_F)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_plan_replays_match_eager_bitwise(graph):
+    import torch
+    w = ragged_mix(seed=43)
+    d = OnDevice(w)
+    p, ts, F, A = _plan(w, d, graph=graph)
+    print(f"case: plan graph={graph} {p.describe()}", flush=True)
+    e_ts, e_F, e_A = _eager(w, d)
+    for rep in range(3):
+        # other work on the stream between replays
+        junk = torch.randn(1 << 20, device="cuda:0").sum()
+        ts.fill_(float("nan"))
+        p.execute()
+        torch.cuda.synchronize()
+        assert torch.equal(ts, e_ts) and torch.equal(F, e_F) and torch.equal(A, e_A), rep
+        del junk
+    # new field contents at the same addresses
+    d.delta.mul_(1.3)
+    d.vpec.add_(5.0)
+    p.execute()
+    torch.cuda.synchronize()
+    w2 = fields.Workload(w.name, d.delta.cpu().numpy(), d.vpec.cpu().numpy(), w.offsets, w.dv,
+                         w.T0, w.gamma, w.target_F, w.window_k)
+    e_ts, e_F, e_A = _eager(w2, OnDevice(w2))
+    assert torch.equal(ts, e_ts) and torch.equal(F, e_F) and torch.equal(A, e_A)
+    assert p.status() == 0
+    raw_ref = oracle_tau(w2)
+    A_g = float(A.cpu())
+    assert_tau_close(ts.cpu().numpy() / A_g, raw_ref, "plan raw tau")
+    assert_F_close(F.cpu().numpy(), np.exp(-A_g * raw_ref), "plan F")
+    p.close()
+
+
+def test_autotune_times_every_candidate_and_caches(tmp_path, monkeypatch):
+    monkeypatch.setenv("LYAF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = ragged_mix(seed=45)
+    d = OnDevice(w)
+    p, ts, F, A = _plan(w, d, autotune=True)
+    info = p.describe()
+    print(f"case: autotune {info}", flush=True)
+    assert info["tuned"] and not info["from_cache"] and info["graph"]
+    assert len(info["timings_us"]) == 8
+    lines = open(tmp_path / "tune.txt").read().split("\n")
+    assert lines[0].startswith(info["key"] + " ")
+    raw_ref = oracle_tau(w)
+    A_g = float(A.cpu())
+    assert_tau_close(ts.cpu().numpy() / A_g, raw_ref, "tuned raw tau")
+    p.close()
+    p2, ts2, F2, A2 = _plan(w, d, autotune=True)
+    info2 = p2.describe()
+    assert info2["from_cache"] and info2["key"] == info["key"]
+    assert (info2["streams"], info2["targets_per_lane"], info2["tile"]) == \
+        (info["streams"], info["targets_per_lane"], info["tile"])
+    p2.close()
+
+
+@pytest.mark.slow
+def test_config3_plan_sampled():
+    """20,000 ragged skewers through one tuned plan (persistent launch in a
+    hipGraph); sampled skewers against the oracle; A through the oracle's
+    root-find on the GPU's rescaled tau (which must give 1)."""
+    import torch
+    w = fields.config3()
+    d = OnDevice(w)
+    p, ts, F, A = _plan(w, d, autotune=True)
+    print(f"case: {w.name} plan {p.describe()}", flush=True)
+    p.execute()
+    torch.cuda.synchronize()
+    A_g = float(A.cpu())
+    ts_np = ts.cpu().numpy()
+    A1, _ = O.mean_flux_A(ts_np.astype(np.float64), w.target_F)
+    assert abs(A1 - 1.0) <= 2 * A_REL
+    lens = np.diff(w.offsets)
+    rng = np.random.default_rng(33)
+    pick = np.unique(np.concatenate([[int(np.argmin(lens)), int(np.argmax(lens))],
+                                     rng.choice(w.n_skewers, 16, replace=False)]))
+    sub = w.subset(pick)
+    ref = oracle_tau(sub)
+    sel = np.concatenate([np.arange(w.offsets[s], w.offsets[s + 1]) for s in pick])
+    assert_tau_close(ts_np[sel] / A_g, ref, "C3 plan raw tau")
+    assert_F_close(F.cpu().numpy()[sel], np.exp(-A_g * ref), "C3 plan F")
+    p.close()
