@@ -111,6 +111,25 @@ def batched_section(L, torch, dev, fields, timed, reps):
                              "frac": round(ach / FP32_PEAK_TFLOPS, 4)}}
 
 
+def measured_traffic(shape: int, persistent: bool, workload: str):
+    """HBM bytes per tau-stage launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, or None when the kernel sources changed since the
+    counters were taken (or this shape/launch/workload was not counted)."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "tau_stage_traffic.json")))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in ("lyaf_tau.hip", "lyaf_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1105_4747_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"] or persistent or \
+            not workload.startswith("C2"):
+        return None
+    ent = rec["per_shape"].get(str(shape))
+    return None if ent is None else ent["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(w, target_seconds=10.0):
     """FP64 oracle on the host: full sum of eq. (6) + mean-flux root-find, on
     the first skewers of the workload, sized to ~target_seconds of wall time."""
@@ -142,6 +161,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"])
+    ap.add_argument("--tau-only", action="store_true",
+                    help="only run the tau stage (reach + windowed kernel) K times, for profiling")
+    ap.add_argument("--shape", type=int, default=None,
+                    help="windowed-kernel shape for --tau-only (LYAF_FLAG_SHAPE); default: tuned")
+    ap.add_argument("--persistent", action="store_true", help="persistent launch in --tau-only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB float32 buffer 3 times (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +202,17 @@ def main():
     F = torch.empty(P, device=dev, dtype=torch.float32)
     A = torch.empty((), device=dev, dtype=torch.float64)
     stream = torch.cuda.current_stream()
+
+    if args.tau_only:
+        shape = 0 if args.shape is None else args.shape
+        fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if args.persistent else 0)
+        for _ in range(args.warmup + args.steps):
+            L.tau(delta, vpec, dvt, T0, gamma, w.offsets, ts, tau_ref=w.tau_ref,
+                  delta_pivot=w.delta_pivot, window_k=w.window_k, flags=fl)
+        torch.cuda.synchronize()
+        print(json.dumps({"tau_only": True, "shape": SHAPES[shape], "persistent": args.persistent,
+                          "launches": args.warmup + args.steps}), flush=True)
+        return
 
     # the whole forward (reach, windowed tau, mean-flux root-find, tau', F) as
     # one tuned plan, replayed from a hipGraph
@@ -238,7 +273,8 @@ def main():
     achieved = pairs * OPS_PER_PAIR / t_tau / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(shape, info["persistent_grid"] > 0, w.name),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE)",
                 "kernel": "tau stage: reach_kernel + " + ("tau_window_persistent_kernel"
                                                           if info["persistent_grid"] > 0
                                                           else "tau_window_kernel"),
