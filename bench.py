@@ -62,9 +62,6 @@ def algorithmic_pairs(w) -> float:
     return total
 
 
-SHAPES = [(8, 4, 512), (8, 4, 256), (16, 4, 512), (8, 2, 512)]  # LYAF_FLAG_SHAPE(v)
-
-
 def batched_section(L, torch, dev, fields, timed, reps):
     """The ragged 20,000-skewer batch (lengths 512-8192 px, dv 1-4 km/s, T0
     and gamma drawn per skewer): one tuned plan (persistent launch in a
@@ -82,8 +79,7 @@ def batched_section(L, torch, dev, fields, timed, reps):
                   window_k=w.window_k, autotune=True)
     info = plan.describe()
     t_plan = timed(plan.execute, reps)
-    shape = [i for i, v in enumerate(SHAPES) if v == (info["streams"], info["targets_per_lane"],
-                                                      info["tile"])][0]
+    shape = info["shape"]
     fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if info["persistent_grid"] > 0 else 0)
     raw = torch.empty_like(ts)
     tau = lambda flags: L.tau(delta, vpec, dvt, T0, gamma, w.offsets, raw,
@@ -109,6 +105,13 @@ def batched_section(L, torch, dev, fields, timed, reps):
             "tau_roofline": {"bound": "alu", "achieved": round(ach, 3),
                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": round(ach / FP32_PEAK_TFLOPS, 4)}}
+
+
+def tau_kernel_name(shape: int, persistent: bool) -> str:
+    """Kernel that LYAF_FLAG_SHAPE(shape) launches: shapes 0-1 are the skewed
+    per-lane-run form, 2-3 the shared-run form with source streams."""
+    base = "tau_skew" if shape < 2 else "tau_window"
+    return base + ("_persistent_kernel" if persistent else "_kernel")
 
 
 def measured_traffic(shape: int, persistent: bool, workload: str):
@@ -210,7 +213,7 @@ def main():
             L.tau(delta, vpec, dvt, T0, gamma, w.offsets, ts, tau_ref=w.tau_ref,
                   delta_pivot=w.delta_pivot, window_k=w.window_k, flags=fl)
         torch.cuda.synchronize()
-        print(json.dumps({"tau_only": True, "shape": SHAPES[shape], "persistent": args.persistent,
+        print(json.dumps({"tau_only": True, "shape": shape, "persistent": args.persistent,
                           "launches": args.warmup + args.steps}), flush=True)
         return
 
@@ -241,8 +244,7 @@ def main():
 
     # the tau stage alone (reach + windowed kernel, the plan's shape and launch
     # form), HIP events on the launch stream
-    shape = [i for i, v in enumerate(SHAPES) if v == (info["streams"], info["targets_per_lane"],
-                                                      info["tile"])][0]
+    shape = info["shape"]
     tau_flags = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if info["persistent_grid"] > 0 else 0)
     raw = torch.empty(P, device=dev, dtype=torch.float32)
 
@@ -275,9 +277,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(shape, info["persistent_grid"] > 0, w.name),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE)",
-                "kernel": "tau stage: reach_kernel + " + ("tau_window_persistent_kernel"
-                                                          if info["persistent_grid"] > 0
-                                                          else "tau_window_kernel"),
+                "kernel": "tau stage: reach_kernel + " + tau_kernel_name(
+                    shape, info["persistent_grid"] > 0),
                 "kernel_ms": round(t_tau * 1e3, 4),
                 "pairs_per_launch": pairs, "pairs_per_px": round(pairs / P, 3),
                 "pair_rate_per_s": pairs / t_tau, "ops_per_pair": OPS_PER_PAIR}

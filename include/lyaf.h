@@ -77,8 +77,10 @@ extern "C" {
 #define LYAF_FLAG_PERSISTENT 4u
 /* Force windowed-kernel shape v (0 .. LYAF_NUM_SHAPES-1; the shapes a plan's
  * tuner chooses from): flags |= LYAF_FLAG_SHAPE(v).  Shape 0 is the default:
- * 8 source streams, 4 targets per lane, 512-pixel tiles; 1: 256-pixel tiles;
- * 2: 16 streams; 3: 2 targets per lane. */
+ * each lane owns 4 consecutive targets and walks its own run of sources, one
+ * source stream per wave, 1024-pixel tiles; 1: the same with 512-pixel tiles;
+ * 2: 8 source streams share 32-target sub-tiles, 4 targets per lane,
+ * 512-pixel tiles; 3: as 2 with 2 targets per lane. */
 #define LYAF_NUM_SHAPES 4
 #define LYAF_FLAG_SHAPE(v) ((((uint32_t)(v)) + 1u) << 8)
 

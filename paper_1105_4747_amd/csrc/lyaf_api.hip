@@ -481,13 +481,13 @@ hipError_t enqueue_forward(lyaf_plan *p, hipStream_t st) {
 
 std::string make_tune_key(const lyaf_plan *p) {
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return "v1|unknown";
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return "v2|unknown";
   const int64_t S = p->sk.n_skewers;
   const double meanN = S > 0 ? (double)p->P / (double)S : 0.0;
   int maxR = 0;
   for (const auto &k : p->skc_host) maxR = std::max(maxR, k.reach);
   char buf[512];
-  snprintf(buf, sizeof(buf), "v1|%s|cu%d|S2^%d|N2^%d|R2^%d|k%g", prop.gcnArchName,
+  snprintf(buf, sizeof(buf), "v2|%s|cu%d|S2^%d|N2^%d|R2^%d|k%g", prop.gcnArchName,
            prop.multiProcessorCount, (int)lround(log2((double)std::max<int64_t>(S, 1))),
            (int)lround(log2(std::max(meanN, 1.0))), (int)lround(log2(std::max(maxR, 1))),
            p->prm.window_k);
@@ -672,10 +672,11 @@ int lyaf_plan_describe(const lyaf_plan *plan, char *buf, int64_t buf_len) {
   t += "]";
   char head[768];
   snprintf(head, sizeof(head),
-           "{\"streams\":%d,\"targets_per_lane\":%d,\"tile\":%d,\"persistent_grid\":%d,"
+           "{\"shape\":%d,\"streams\":%d,\"targets_per_lane\":%d,\"tile\":%d,"
+           "\"persistent_grid\":%d,"
            "\"items\":%lld,\"graph\":%s,\"tuned\":%s,\"from_cache\":%s,\"key\":\"%s\","
            "\"timings_us\":",
-           v.S, v.M, v.tile, plan->persistent_grid, (long long)plan->n_items,
+           plan->variant, v.S, v.M, v.tile, plan->persistent_grid, (long long)plan->n_items,
            plan->exec ? "true" : "false", plan->tuned ? "true" : "false",
            plan->from_cache ? "true" : "false", plan->tune_key.c_str());
   std::string out = std::string(head) + t + "}";

@@ -4,19 +4,25 @@
 //   reach_kernel        one workgroup per skewer: per-skewer constants in FP64,
 //                       the largest velocity-space reach (|v_j| + k b_j) / dv in
 //                       pixels, and the device-side domain checks.
-//   tau_window_kernel   one workgroup per target tile.  The sources that can
-//                       reach the tile (tile +- reach) are staged once into
-//                       LDS as (w, r, v, a = dv r) plus the window bounds of
-//                       every group of S sources.  Each wave splits into S
-//                       source streams of 64/S lanes; a lane owns M
-//                       consecutive targets and evaluates, per source, one
-//                       exact FMA for the velocity offset and one exp2 per
-//                       pair.  A wave visits only the contiguous run of groups
-//                       whose windows reach its targets.  Streams sum in FP32
-//                       with a blocked Kahan fold and meet in a DPP butterfly.
-//                       Short or very wide skewers (tile + 2 reach > N) take a
-//                       full-sum path over every source with the minimal
-//                       periodic image chosen per pair.
+//   tau_skew_kernel     one workgroup per tile of 1024 (or 512) targets; the
+//                       default form.  The sources that can reach the tile
+//                       (tile +- reach) are staged once into LDS as
+//                       (w, r, v, a = dv r) in four planes by index mod 4,
+//                       with each source's window bounds.  A lane owns 4
+//                       consecutive targets and walks its own run of sources,
+//                       shifted with its targets, whose start and length are
+//                       uniform over the wave and come from the window bounds
+//                       of the sources that meet the wave's 256 targets.  Per
+//                       source and lane: one exact FMA for the velocity
+//                       offset, one exp2 per pair, FP32 sums with a blocked
+//                       Kahan fold every 16 terms; no cross-lane reduction.
+//   tau_window_kernel   the earlier shared-run form: a wave splits into S
+//                       source streams that share a sub-tile of 64 M / S
+//                       targets, visits the contiguous run of source groups
+//                       whose windows reach it, and sums the streams in a DPP
+//                       butterfly.
+//   Short or very wide skewers (tile + 2 reach > N) take a full-sum path over
+//   every source with the minimal periodic image chosen per pair.
 //   tau_plain_kernel    the literal full O(N^2) sum, one thread per target,
 //                       naive FP32 accumulation (the comparison baseline).
 #include <math.h>
@@ -378,7 +384,10 @@ __global__ __launch_bounds__(kTauThreads) void tau_window_kernel(Batch b,
 
 // Persistent form: a grid sized to the resident workgroups takes items from a
 // queue (the work list is sorted by estimated cost, largest first) until it is
-// empty; every workgroup leaves the loop once the counter passes n_items.
+// empty; every workgroup leaves the loop once the counter passes n_items.  A
+// workgroup takes kQueueGrab consecutive items per atomic: the counter lives
+// beyond the per-die L2 caches, and one increment per item serialises there.
+constexpr int kQueueGrab = 4;
 template <int S, int M, int TILE>
 __global__ __launch_bounds__(kTauThreads) void tau_window_persistent_kernel(
     Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
@@ -388,20 +397,300 @@ __global__ __launch_bounds__(kTauThreads) void tau_window_persistent_kernel(
   __shared__ int next;
   for (;;) {
     __syncthreads();  // the previous item is done with LDS and `next`
-    if (threadIdx.x == 0) next = (int)atomicAdd(queue, 1u);
+    if (threadIdx.x == 0) next = (int)atomicAdd(queue, (unsigned)kQueueGrab);
     __syncthreads();
-    const int idx = next;
-    if (idx >= n_items) break;
-    tau_tile<S, M, TILE>(b, items[idx], tau, rec, bnd);
+    const int first = next;
+    if (first >= n_items) break;
+    const int last = min(first + kQueueGrab, n_items);
+    for (int idx = first; idx < last; ++idx) {
+      if (idx > first) __syncthreads();  // the previous item is done with LDS
+      tau_tile<S, M, TILE>(b, items[idx], tau, rec, bnd);
+    }
   }
 }
 
 __global__ void reset_queue_kernel(unsigned int *queue) { *queue = 0u; }
 
+// ---------------------------------------------------------------------------
+// Skewed windowed tile.  One source stream per wave: lane l owns the kSkewM
+// consecutive targets i_l = t0 + 4l .. i_l + 3 of the wave's 256-target span
+// and walks its own run of sources e = i_l - H .. i_l - H + NS - 1, where H
+// and NS are wave-uniform.  The run therefore moves with the lane's targets:
+// target minus source is the same integer H - s on every lane at step s, so
+// no lane sees sources that only its neighbours need, and each lane finishes
+// with its own sums (no cross-lane reduction).  H and NS come from a scan of
+// the staged window bounds: H is the largest (lane start - source) and
+// NS - H the largest (source - lane start) over the source/lane pairs whose
+// window and targets meet.  Sources are staged in four planes by extended
+// index mod 4, so the 64 lanes of a step read 64 consecutive float4 (no bank
+// conflicts) and the four steps of an unrolled block use immediate offsets.
+constexpr int kSkewM = 4;                  // targets per lane
+constexpr int kSkewSpan = kWave * kSkewM;  // targets per wave
+constexpr int kSkewFold = 16;              // Kahan fold period (terms per run)
+constexpr int kSkewMargin = 12;            // staged sources beyond the reach
+constexpr int kSkewGroup = 8;              // sources per window-bounds group
+// Target-minus-source offsets as exact floats, read from LDS four at a time
+// (one broadcast read per block of four steps instead of a VALU decrement per
+// step): entry k holds kFdTop - k.  A lane run covers offsets H4 .. H4 - NS + 1
+// with H4 <= RH <= 476 and NS <= H4 + RH + 4, plus one block read ahead.
+constexpr int kSkewMaxRH = 476;  // staged margin limit of the windowed path
+constexpr int kFdTop = 480;
+constexpr int kFdN = 976;
+static_assert(kFdTop >= kSkewMaxRH + 4 && kFdN >= kFdTop + kSkewMaxRH + 8 && kFdN % 4 == 0,
+              "offset table covers every lane run");
+
+template <int NWAVES>
+struct SkewShape {
+  static constexpr int kThreads = NWAVES * kWave;
+  static constexpr int kTile = NWAVES * kSkewSpan;
+  // staged sources: tile + 2 RH with RH <= 476, so that five 4-wave
+  // workgroups fit in the 160 KiB of LDS of a compute unit
+  static constexpr int kChunkS = kTile + 952 > kChunk ? kTile + 952 : kChunk;
+  static constexpr int kPlane = kChunkS / 4;
+  static constexpr int kGroups = kChunkS / kSkewGroup;
+  static_assert(kChunkS >= kChunk, "the full-sum path stages kChunk sources");
+};
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m));
+  return x;
+}
+
+template <int NWAVES>
+__device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
+                                              float *__restrict__ tau, float4 *rec,
+                                              int *gwin, const float4 *fdt) {
+  using SH = SkewShape<NWAVES>;
+  constexpr int TILE = SH::kTile, NT = SH::kThreads, PL = SH::kPlane;
+  const int64_t s = item.x;
+  const int i0 = item.y * TILE;
+  const SkewerConst K = b.skc[s];
+  const int64_t off = b.offsets[s];
+  const int n = K.n;
+  const int i_end = min(i0 + TILE, n);
+  // staged margin on each side, a multiple of 4 so that lane runs start on a
+  // plane-0 column
+  const int RH = (K.reach + kSkewMargin + 3) & ~3;
+  if (TILE + 2 * RH > SH::kChunkS || RH > kSkewMaxRH || 2 * RH + 8 > n) {
+    // the window covers the box, or reaches beyond the staged margin
+    for (int q = i0; q < i_end; q += NT) full_sum_tile<true>(b, K, off, q, tau, rec);
+    return;
+  }
+
+  // ---- stage extended indices e_lo .. i_end + RH - 1 (position c = e - e_lo).
+  // A thread issues its global reads in rounds of 8 ahead of the arithmetic
+  // of the round.  The
+  // window bounds of every group of 8 positions (lowest ceil(lo), highest
+  // floor(hi)) meet in a DPP reduction over the 8 lanes that hold them.
+  constexpr int SIT = 8;  // positions per thread per round of reads
+  const int e_lo = i0 - RH;
+  const int cnt = (i_end - i0) + 2 * RH;
+  const float pivot = b.pivot, wk = b.window_k;
+  for (int c0 = 0; c0 < cnt; c0 += SIT * NT) {
+    float dd[SIT], vv[SIT];
+#pragma unroll
+    for (int u = 0; u < SIT; ++u) {
+      const int c = c0 + threadIdx.x + u * NT;
+      dd[u] = 0.f;
+      vv[u] = 0.f;
+      if (c < cnt) {
+        const int e = e_lo + c;  // -n <= e < 2n: RH <= n/2 and i_end <= n
+        const int j = e < 0 ? e + n : (e >= n ? e - n : e);
+        dd[u] = b.delta[off + j];
+        vv[u] = b.vpec[off + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SIT; ++u) {
+      if (c0 + u * NT >= cnt) break;
+      const int c = c0 + threadIdx.x + u * NT;
+      const Src o = source_of(dd[u], K, pivot);
+      float flo = 8191.f, fhi = -8192.f;  // no window: meets no target
+      if (c < cnt) {
+        if (o.w > 0.f) {
+          const float cc = __builtin_fmaf(vv[u], K.inv_dv, (float)c);  // line centre
+          const float h = wk * o.b * K.inv_dv;                         // half window
+          flo = fminf(fmaxf(ceilf(cc - h), -8192.f), 8191.f);
+          fhi = fminf(fmaxf(floorf(cc + h), -8192.f), 8191.f);
+        }
+        rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], K.dv * o.r);
+      }
+      flo = stream_min<kSkewGroup>(flo);
+      fhi = stream_max<kSkewGroup>(fhi);
+      if ((threadIdx.x & (kSkewGroup - 1)) == 0 && c < cnt)
+        gwin[c / kSkewGroup] =
+            (int)(((uint32_t)(int)fhi & 0xFFFFu) | ((uint32_t)(int)flo << 16));
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int t0 = i0 + wave * kSkewSpan;
+  if (t0 >= i_end) return;
+  const int T0r = t0 - e_lo;  // position of the wave's first target
+  const int last_lane = min(kWave - 1, (i_end - 1 - t0) >> 2);
+
+  // ---- H and NS for this wave, from the groups whose windows meet its
+  // targets: the group's first position bounds (lane start - source) from
+  // above, its last position (source - lane start)
+  int Hm = -(1 << 20), Em = -(1 << 20);
+  {
+    const int g_beg = (T0r - RH) / kSkewGroup;
+    const int g_end = min((cnt + kSkewGroup - 1) / kSkewGroup,
+                          (T0r + kSkewSpan + RH + kSkewGroup - 1) / kSkewGroup);
+    for (int g = g_beg + lane; g < g_end; g += kWave) {
+      const int x = gwin[g];
+      const int fh = (int)(int16_t)(x & 0xFFFF) - T0r;  // floor(hi) - T0r
+      const int fl = (x >> 16) - (kSkewM - 1) - T0r;
+      const int lhi = min(fh >> 2, last_lane);  // last lane whose targets the windows meet
+      const int llo = max((fl + 3) >> 2, 0);    // first such lane
+      if (llo <= lhi) {
+        Hm = max(Hm, T0r + 4 * lhi - kSkewGroup * g);
+        Em = max(Em, kSkewGroup * g + kSkewGroup - 1 - T0r - 4 * llo);
+      }
+    }
+    Hm = __builtin_amdgcn_readfirstlane(wave_max(Hm));
+    Em = __builtin_amdgcn_readfirstlane(wave_max(Em));
+  }
+  const int H4 = min((Hm + 3) & ~3, RH);
+  const int NS = min((H4 + Em + 1 + 3) & ~3, H4 + RH + 4);
+  const int i_l = t0 + kSkewM * lane;
+
+  float sum[kSkewM], comp[kSkewM];
+#pragma unroll
+  for (int k = 0; k < kSkewM; ++k) sum[k] = comp[k] = 0.f;
+  if (Em >= -(1 << 19) && NS > 0) {
+    const float dv = K.dv;
+    float acc[kSkewM];
+    // one source against the lane's kSkewM targets; fd is the exact target
+    // minus source offset of the step; FIRST starts a new run
+    auto pair_step = [&](const float4 q, const float fd, const bool first) {
+      const float d0 = __builtin_fmaf(fd, dv, -q.z);
+      const float tt0 = d0 * q.y;
+#pragma unroll
+      for (int k = 0; k < kSkewM; ++k) {
+        const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, q.w, tt0);
+        const float e = fexp2(-(t * t));
+        acc[k] = first ? q.x * e : __builtin_fmaf(q.x, e, acc[k]);
+      }
+    };
+    auto block = [&](const float4 (&q)[5], const bool first) {
+      pair_step(q[0], q[4].x, first);
+      pair_step(q[1], q[4].y, false);
+      pair_step(q[2], q[4].z, false);
+      pair_step(q[3], q[4].w, false);
+      // v_exp_f32 takes about two and a half VALU issue slots and does not
+      // overlap other VALU work of the wave: spread the block's 16 exps, one
+      // per four other VALU instructions
+#pragma unroll
+      for (int z = 0; z < 4 * kSkewM; ++z) {
+        __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // four VALU
+      }
+    };
+    auto fold = [&]() {
+#pragma unroll
+      for (int k = 0; k < kSkewM; ++k) {
+        const float y = acc[k] - comp[k];
+        const float tt = sum[k] + y;
+        comp[k] = (tt - sum[k]) - y;
+        sum[k] = tt;
+      }
+    };
+    // column of the run's first source in every plane; a block is 4 steps
+    // (one record from each plane), a run of kSkewFold steps is 4 blocks
+    const float4 *p = rec + ((T0r - H4) >> 2) + lane;
+    const float4 *pf = fdt + ((kFdTop - H4) >> 2);  // offsets H4 - 4 blk - (0..3)
+    auto load = [&](float4 (&q)[5], const int blk) {
+      q[0] = p[blk];
+      q[1] = p[blk + PL];
+      q[2] = p[blk + 2 * PL];
+      q[3] = p[blk + 3 * PL];
+      q[4] = pf[blk];
+    };
+    const int nblk = NS >> 2;
+    // the next block's records are read while this one is evaluated; the read
+    // past the last block stays inside the staged array
+    float4 qa[5], qb[5];
+    load(qa, 0);
+    int blk = 0;
+    for (; blk + 4 <= nblk; blk += 4) {
+      load(qb, blk + 1);
+      block(qa, true);
+      load(qa, blk + 2);
+      block(qb, false);
+      load(qb, blk + 3);
+      block(qa, false);
+      load(qa, blk + 4);
+      block(qb, false);
+      fold();
+    }
+    for (; blk < nblk; ++blk) {
+      load(qb, blk + 1);
+      block(qa, true);
+      fold();
+#pragma unroll
+      for (int k = 0; k < 5; ++k) qa[k] = qb[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kSkewM; ++k) {
+    const int i = i_l + k;
+    if (i < i_end) tau[off + i] = sum[k] - comp[k];
+  }
+}
+
+__device__ __forceinline__ void fill_offset_table(float4 *fdt) {
+  for (int k = threadIdx.x; k < kFdN / 4; k += blockDim.x) {
+    const float t = (float)(kFdTop - 4 * k);
+    fdt[k] = make_float4(t, t - 1.f, t - 2.f, t - 3.f);
+  }
+}
+
+template <int NWAVES>
+__global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
+                                                                  const int2 *__restrict__ items,
+                                                                  float *__restrict__ tau) {
+  __shared__ float4 rec[SkewShape<NWAVES>::kChunkS + 4];
+  __shared__ int gwin[SkewShape<NWAVES>::kGroups];
+  __shared__ float4 fdt[kFdN / 4];
+  fill_offset_table(fdt);  // published by the barrier after staging
+  tau_skew_tile<NWAVES>(b, items[blockIdx.x], tau, rec, gwin, fdt);
+}
+
+// 4-wave form: at most 128 VGPRs, so that four waves share a SIMD as in the
+// grid form
+template <int NWAVES>
+__global__ __launch_bounds__(NWAVES * kWave)
+__attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
+    Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
+    float *__restrict__ tau) {
+  __shared__ float4 rec[SkewShape<NWAVES>::kChunkS + 4];
+  __shared__ int gwin[SkewShape<NWAVES>::kGroups];
+  __shared__ float4 fdt[kFdN / 4];
+  __shared__ int next;
+  fill_offset_table(fdt);
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS and `next`
+    if (threadIdx.x == 0) next = (int)atomicAdd(queue, (unsigned)kQueueGrab);
+    __syncthreads();
+    const int first = next;
+    if (first >= n_items) break;
+    const int last = min(first + kQueueGrab, n_items);
+    for (int idx = first; idx < last; ++idx) {
+      if (idx > first) __syncthreads();  // the previous item is done with LDS
+      tau_skew_tile<NWAVES>(b, items[idx], tau, rec, gwin, fdt);
+    }
+  }
+}
+
 namespace {
 struct VariantFns {
   const void *grid_fn;
   const void *pers_fn;
+  int threads;
   void (*grid)(const Batch &, const int2 *, int64_t, float *, hipStream_t);
   void (*pers)(const Batch &, const int2 *, int64_t, unsigned int *, int, float *, hipStream_t);
 };
@@ -411,6 +700,7 @@ VariantFns make_variant() {
   VariantFns v;
   v.grid_fn = reinterpret_cast<const void *>(&tau_window_kernel<S, M, TILE>);
   v.pers_fn = reinterpret_cast<const void *>(&tau_window_persistent_kernel<S, M, TILE>);
+  v.threads = kTauThreads;
   v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
     hipLaunchKernelGGL((tau_window_kernel<S, M, TILE>), dim3((unsigned)n), dim3(kTauThreads), 0,
                        st, b, items, tau);
@@ -424,11 +714,31 @@ VariantFns make_variant() {
   return v;
 }
 
+template <int NWAVES>
+VariantFns make_skew_variant() {
+  constexpr int NT = SkewShape<NWAVES>::kThreads;
+  VariantFns v;
+  v.grid_fn = reinterpret_cast<const void *>(&tau_skew_kernel<NWAVES>);
+  v.pers_fn = reinterpret_cast<const void *>(&tau_skew_persistent_kernel<NWAVES>);
+  v.threads = NT;
+  v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
+    hipLaunchKernelGGL((tau_skew_kernel<NWAVES>), dim3((unsigned)n), dim3(NT), 0, st, b, items,
+                       tau);
+  };
+  v.pers = [](const Batch &b, const int2 *items, int64_t n, unsigned int *queue, int grid,
+              float *tau, hipStream_t st) {
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, queue);
+    hipLaunchKernelGGL((tau_skew_persistent_kernel<NWAVES>), dim3((unsigned)grid), dim3(NT), 0,
+                       st, b, items, (int)n, queue, tau);
+  };
+  return v;
+}
+
 const VariantFns &variant_fns(int v) {
   static const VariantFns table[kNumTauVariants] = {
-      make_variant<8, 4, 512>(),   // kTauVariantDefault
-      make_variant<8, 4, 256>(),
-      make_variant<16, 4, 512>(),
+      make_skew_variant<4>(),      // kTauVariantDefault
+      make_skew_variant<2>(),
+      make_variant<8, 4, 512>(),
       make_variant<8, 2, 512>(),
   };
   return table[v];
@@ -436,7 +746,7 @@ const VariantFns &variant_fns(int v) {
 }  // namespace
 
 const TauVariant kTauVariants[kNumTauVariants] = {
-    {8, 4, 512}, {8, 4, 256}, {16, 4, 512}, {8, 2, 512}};
+    {1, kSkewM, SkewShape<4>::kTile}, {1, kSkewM, SkewShape<2>::kTile}, {8, 4, 512}, {8, 2, 512}};
 
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items, float *tau,
                              hipStream_t st, int variant, int persistent_grid,
@@ -455,8 +765,9 @@ int tau_persistent_grid(int variant) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, variant_fns(variant).pers_fn,
-                                                   kTauThreads, 0) != hipSuccess)
+  const VariantFns &f = variant_fns(variant);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f.pers_fn, f.threads, 0) !=
+      hipSuccess)
     return 0;
   return std::max(1, cus * per_cu);
 }
