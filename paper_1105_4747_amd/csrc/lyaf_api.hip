@@ -89,11 +89,11 @@ int get_ws(hipStream_t st, Workspace **out) {
   w->device = dev;
   w->stream = st;
   if ((e = hipMalloc((void **)&w->status, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMalloc((void **)&w->partials, sizeof(double) * 8 * kMaxPartialBlocks)) != hipSuccess ||
-      (e = hipMalloc((void **)&w->norm, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
+      (e = hipMalloc((void **)&w->partials, sizeof(double) * kPartialsDoubles)) != hipSuccess ||
+      (e = hipMalloc((void **)&w->norm, sizeof(NormState) * (kNormPasses + 2))) != hipSuccess ||
       (e = hipMalloc((void **)&w->ratio, sizeof(double))) != hipSuccess ||
       (e = hipMemset(w->status, 0, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMemset(w->norm, 0, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
+      (e = hipMemset(w->norm, 0, sizeof(NormState) * (kNormPasses + 2))) != hipSuccess ||
       (e = hipMemset(w->ratio, 0, sizeof(double))) != hipSuccess) {
     delete w;
     return map_err(e);
@@ -568,12 +568,12 @@ int lyaf_plan_create(const lyaf_skewers *sk, const lyaf_params *prm, double targ
   if ((e = grow_dev(p->ws.offsets, p->ws.off_cap, S + 1)) != hipSuccess ||
       (e = grow_dev(p->ws.skc, p->ws.skc_cap, S)) != hipSuccess ||
       (e = hipMalloc((void **)&p->ws.status, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMalloc((void **)&p->ws.partials, sizeof(double) * 8 * kMaxPartialBlocks)) != hipSuccess ||
-      (e = hipMalloc((void **)&p->ws.norm, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
+      (e = hipMalloc((void **)&p->ws.partials, sizeof(double) * kPartialsDoubles)) != hipSuccess ||
+      (e = hipMalloc((void **)&p->ws.norm, sizeof(NormState) * (kNormPasses + 2))) != hipSuccess ||
       (e = hipMalloc((void **)&p->ws.ratio, sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void **)&p->queue, sizeof(unsigned int))) != hipSuccess ||
       (e = hipMemset(p->ws.status, 0, sizeof(uint32_t))) != hipSuccess ||
-      (e = hipMemset(p->ws.norm, 0, sizeof(NormState) * (kNormMaxIter + 2))) != hipSuccess ||
+      (e = hipMemset(p->ws.norm, 0, sizeof(NormState) * (kNormPasses + 2))) != hipSuccess ||
       (e = hipMemset(p->queue, 0, sizeof(unsigned int))) != hipSuccess ||
       (e = hipMemcpy(p->ws.offsets, p->offsets.data(), sizeof(int64_t) * (S + 1),
                      hipMemcpyHostToDevice)) != hipSuccess) {

@@ -45,21 +45,28 @@ struct SkewerConst {
   int32_t n;     // pixels in the skewer
 };
 
-// Mean-flux root-find state (device).
+// Mean-flux root-find state (device).  The iteration runs on a sample of the
+// pixels, then with FP32 moments over all pixels, then FP64 moments.
 struct NormState {
-  double A, lo, hi;
-  double P, target;
+  double A, lo, hi;  // iterate and bracket
+  double P, Ps;      // pixels in the batch and in the sample
+  double target;
+  double step;       // |A_new - A_old| / A_new of the last step
   int32_t iter, done, status;
-  int32_t exact;  // 0: moments with FP32 exp2 (approach), 1: FP64 exp (final steps)
+  int32_t phase;     // kNormPhaseFP32, kNormPhaseExact
+  int32_t pending;   // no moments at A yet (the next full pass computes them)
+  int32_t buf;       // partial buffer (0 or 1) holding the last moments
+  int32_t nparts;    // workgroups that wrote them
 };
+constexpr int32_t kNormPhaseFP32 = 1, kNormPhaseExact = 2;
 
 // Per-(device, stream) workspace.
 struct Workspace {
   int device = -1;
   hipStream_t stream = nullptr;
   uint32_t *status = nullptr;       // sticky LYAF_STATUS_* bits
-  double *partials = nullptr;       // [2 * kMaxPartialBlocks * 4]
-  NormState *norm = nullptr;        // [kNormMaxIter + 2]
+  double *partials = nullptr;       // [kPartialsDoubles]
+  NormState *norm = nullptr;        // [kNormPasses + 2]
   double *ratio = nullptr;          // backward-normalise scalar
   // growable buffers
   SkewerConst *skc = nullptr;  int64_t skc_cap = 0;
@@ -69,8 +76,13 @@ struct Workspace {
   double *gpart = nullptr;     int64_t gpart_cap = 0;  // adjoint per-item FP64 partials
   unsigned int *queue = nullptr;                      // persistent work-queue counter
 };
-constexpr int kMaxPartialBlocks = 1024;
-constexpr int kNormMaxIter = 7;
+constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
+constexpr int kPartStride = 8;          // doubles per workgroup partial
+constexpr int kNormPasses = 3;          // full root-find passes after the sample
+constexpr int kSampleN = 16384;         // pixels the root-find samples first
+// The partials allocation also holds the sample (kSampleN floats) after the
+// two partial buffers.
+constexpr int64_t kPartialsDoubles = 2 * kPartStride * kMaxPartialBlocks + kSampleN / 2;
 constexpr double kNormAcceptStep = 1e-5;
 
 // Kernel-side view of a skewer batch.

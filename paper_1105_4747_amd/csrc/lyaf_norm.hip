@@ -2,19 +2,35 @@
 // Wyithe 2011): find A with (1/P) sum_p exp(-A tau_p) = target_F over all
 // pixels, then tau' = A tau and F = exp(-tau'); plus its backward pass.
 //
-// The root-find runs on the device without host synchronisation: one pass
-// (norm_init) forms sum tau, the count of tau = 0 pixels and the domain check,
-// and starts from the Jensen lower bound A0 = -ln F / <tau> (g(A0) >= 0, and g
-// is convex and decreasing, so Newton steps from the left never overshoot).
-// Each further pass evaluates S_k = sum tau^k exp(-A tau), k = 0, 1, 2, in FP64
-// per workgroup.  The next pass (or the finalise kernel) begins with every
-// workgroup summing those partials in the same fixed order and taking the
-// same safeguarded Halley step (Newton, then bisection, as fallbacks) inside
-// the bracket.  A kernel boundary, not a device-scope fence, publishes the
-// partials: on a multi-XCD part a fence per workgroup writes back and
-// invalidates L2 and serialises the pass.  A fixed number of passes is
-// enqueued; once converged the remaining ones return at once.  Results are
-// bitwise reproducible.
+// The root-find runs on the device without host synchronisation, as a short
+// fixed sequence of kernels (each kernel boundary costs a few microseconds,
+// so there are few):
+//   norm_gather    16384 pixels spread evenly over the batch (all of them if
+//                  fewer) into a contiguous buffer;
+//   norm_sample    one workgroup keeps the sample in registers and iterates
+//                  to convergence on it, starting from the Jensen
+//                  lower bound A0 = -ln F / <tau> (g(A0) >= 0 for the convex,
+//                  decreasing g(A) = <exp(-A tau)> - F); FP32 exponentials,
+//                  FP64 sums.  The sample's root is within ~1.5e-2 of the
+//                  batch's (the sampling error of g is ~3e-3).
+//   norm_pass x3   S_k = sum tau^k exp(-A tau), k = 0, 1, 2, over every
+//                  pixel, in FP64 per workgroup, with the counts of zero and
+//                  invalid values; FP32 exponentials until a step is below
+//                  3e-2 of A, then FP64 exponentials (to 1e-13) until a step
+//                  is below 1e-5.  Each pass begins with every workgroup summing the
+//                  previous pass's partials in the same fixed order and taking
+//                  the same safeguarded Halley step (Newton, then bisection,
+//                  as fallbacks) inside the bracket.  A kernel boundary, not a
+//                  device-scope fence, publishes the partials: on a multi-XCD
+//                  part a fence per workgroup writes back and invalidates L2
+//                  and serialises the pass.
+//   norm_finalise  the last step, then tau' = A tau and F = exp(-tau').
+// Halley converges cubically: a step of 3e-2 leaves an iterate ~K 3e-5 off
+// (K, the ratio of successive errors to the cube, is below 0.1 on
+// lognormal-field tau), so one FP32 pass and one FP64 pass usually suffice
+// and the FP64 step that follows is accepted; the third pass is a reserve,
+// and a pass with nothing left to do returns at once.  Results are bitwise
+// reproducible.
 #include <math.h>
 
 #include "lyaf_internal.h"
@@ -24,11 +40,17 @@ namespace lyaf {
 // exp(-x) for x >= 0 in FP64: Cody-Waite reduction x = k ln2 + r with
 // |r| <= ln2/2 (ln2 split into a 32-bit head and a tail so k*ln2_hi is exact),
 // then the Taylor series of exp(-r) to degree 13 (truncation below 1e-17).
+// Full-rate FP64 arithmetic only: adding 1.5 2^52 inside one FMA rounds
+// x log2 e to the integer k, which the low word of that sum holds, and 2^-k
+// is built from its exponent bits.  Below 2^-1021 (x > 708) the result is 0.
 __device__ __forceinline__ double exp_neg(double x) {
-  if (!(x <= 745.2)) return 0.0;
+  if (!(x <= 708.0)) return 0.0;
   const double ln2_hi = 6.93147180369123816490e-01;
   const double ln2_lo = 1.90821492927058770002e-10;
-  const double k = rint(x * kLog2e);
+  const double shifter = 6755399441055744.0;  // 1.5 2^52
+  const double t = fma(x, kLog2e, shifter);
+  const double k = t - shifter;
+  const int ki = __double2loint(t);
   double r = fma(-k, ln2_hi, x);
   r = fma(-k, ln2_lo, r);
   const double y = -r;
@@ -46,282 +68,410 @@ __device__ __forceinline__ double exp_neg(double x) {
   p = fma(p, y, 0.5);
   p = fma(p, y, 1.0);
   p = fma(p, y, 1.0);
-  return ldexp(p, -(int)k);
+  return p * __hiloint2double((1023 - ki) << 20, 0);  // p 2^-k
 }
 
-// exp(-x) for x >= 0 with FP64 argument reduction and the FP32 hardware
-// exp2 on the fraction: x log2 e = n + f, f in [0, 1), result 2^-n * 2^-f.
-// Relative error below 1e-7 (rounding f to FP32 and the exp2 unit); used for
-// the approach iterations only.
-__device__ __forceinline__ double exp_neg_fast(double y /* = x log2 e */) {
-  if (!(y <= 1074.0)) return 0.0;
-  const double nf = floor(y);
-  const float f = (float)(y - nf);
-  return ldexp((double)__builtin_amdgcn_exp2f(-f), -(int)nf);
+// exp(-x) for x >= 0 to 1e-13 relative (the moments of the exact phase need
+// ~1e-10): x = (n/64) ln2 + r with |r| <= ln2/128, 2^(-n/64) =
+// 2^-(n >> 6) tab[n & 63] with tab[j] = 2^(-j/64), and exp(-r) by its Taylor
+// series to degree 4 (truncation below 4e-14).  Below 2^-1021 the result is 0.
+__device__ __forceinline__ double exp_neg_tab(double x, const double *tab) {
+  const double xc = fmin(x, 708.0);  // branch-free: the select below returns 0
+  const double shifter = 6755399441055744.0;  // 1.5 2^52
+  const double t = fma(xc, 64.0 * kLog2e, shifter);
+  const double n = t - shifter;
+  const int ni = __double2loint(t);
+  const double r = fma(-n, kLn2 / 64.0, xc);
+  double p = 1.0 / 24.0;
+  p = fma(p, -r, 1.0 / 6.0);
+  p = fma(p, -r, 0.5);
+  p = fma(p, -r, 1.0);
+  p = fma(p, -r, 1.0);
+  const double e = tab[ni & 63] * p * __hiloint2double((1023 - (ni >> 6)) << 20, 0);
+  return (x <= 708.0) ? e : 0.0;
 }
 
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], double *sh /*[N*4]*/) {
+// Sum of N values over a workgroup of NW waves (fixed order).
+template <int N, int NW>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *sh /*[N*NW]*/) {
 #pragma unroll
   for (int q = 0; q < N; ++q)
     for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int q = 0; q < N; ++q) sh[q * 4 + w] = v[q];
+    for (int q = 0; q < N; ++q) sh[q * NW + w] = v[q];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = (sh[q * 4 + 0] + sh[q * 4 + 1]) + (sh[q * 4 + 2] + sh[q * 4 + 3]);
+  for (int q = 0; q < N; ++q) {
+    double t = sh[q * NW];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) t += sh[q * NW + k];
+    v[q] = t;
+  }
   __syncthreads();
 }
 
 // Fixed-order reduction of NQ partial quantities written per workgroup.
-template <int NQ>
+template <int NQ, int NW>
 __device__ __forceinline__ void reduce_partials(const double *partials, int nblocks,
                                                 double (&tot)[NQ], double *sh) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q) tot[q] = 0.0;
   for (int k = threadIdx.x; k < nblocks; k += blockDim.x)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) tot[q] += partials[k * 4 + q];
-  block_sum<NQ>(tot, sh);
+    for (int q = 0; q < NQ; ++q) tot[q] += partials[k * kPartStride + q];
+  block_sum<NQ, NW>(tot, sh);
 }
 
-constexpr int kNormThreads = 256;
+constexpr int kNormThreads = 256;  // backward kernels and finalise
+constexpr int kNormWaves = kNormThreads / kWave;
+constexpr int kPassThreads = 512;  // full root-find passes
+constexpr int kPassWaves = kPassThreads / kWave;
+constexpr int kNormQ = 5;          // S0, S1, S2, #(tau = 0), #(invalid tau)
+constexpr int kSampleThreads = 256;
+constexpr int kSampleWaves = kSampleThreads / kWave;
+constexpr int kGatherThreads = 256;
+constexpr int kSampleIters = 32;
+// the sample iteration stops at this step: its root is only ~1e-2 from the
+// batch's, and FP32 moments would not let it settle much below 1e-7
+constexpr double kSampleTol = 1e-4;
+constexpr double kFP32Accept = 3e-2;
 
-// Pass 0: sum tau, count tau == 0 and count invalid values, per workgroup.
-__global__ __launch_bounds__(kNormThreads) void norm_init_kernel(const float *__restrict__ tau,
-                                                                 int64_t P, double *partials) {
-  __shared__ double sh[16];
-  double v[3] = {0.0, 0.0, 0.0};  // sum tau, #zeros, #bad
-  auto add = [&](float t) {
-    if (!(t >= 0.f) || !isfinite(t)) v[2] += 1.0;
-    else {
-      v[0] += (double)t;
-      v[1] += (t == 0.f) ? 1.0 : 0.0;
-    }
-  };
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t done_to = 0;
-  if ((reinterpret_cast<uintptr_t>(tau) & 15) == 0) {
-    const int64_t P4 = P >> 2;
-    const float4 *t4 = reinterpret_cast<const float4 *>(tau);
-    int64_t p = base;
-    for (; p + stride < P4; p += 2 * stride) {
-      const float4 qa = t4[p], qb = t4[p + stride];
-      add(qa.x); add(qa.y); add(qa.z); add(qa.w);
-      add(qb.x); add(qb.y); add(qb.z); add(qb.w);
-    }
-    for (; p < P4; p += stride) {
-      const float4 qa = t4[p];
-      add(qa.x); add(qa.y); add(qa.z); add(qa.w);
-    }
-    done_to = P4 << 2;
-  }
-  for (int64_t p = done_to + base; p < P; p += stride) add(tau[p]);
-  block_sum<3>(v, sh);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x * 4 + 0] = v[0];
-    partials[blockIdx.x * 4 + 1] = v[1];
-    partials[blockIdx.x * 4 + 2] = v[2];
-  }
-}
-
-// Starting state from the pass-0 sums: the Jensen lower bound
-// A0 = -ln F / <tau> (g(A0) >= 0), or a terminal state with a status bit.
-__device__ NormState norm_start(const double (&tot)[3], double P, double target) {
-  NormState s;
-  s.P = P;
-  s.target = target;
-  s.iter = 0;
-  s.done = 0;
-  s.status = 0;
-  s.exact = 0;
-  s.lo = 0.0;
-  s.hi = INFINITY;
-  s.A = -log(target) / (tot[0] / P);
-  if (tot[2] > 0.0) {
-    s.done = 1;
-    s.status = LYAF_STATUS_DOMAIN;
-  } else if (!(tot[1] / P < target)) {
-    s.done = 1;
-    s.status = LYAF_STATUS_NOROOT;
-  }
-  return s;
-}
-
-// One safeguarded Halley step from the moments S0, S1, S2 at s.A.
-__device__ NormState norm_step(NormState s, const double (&tot)[3]) {
-  const double g = tot[0] / s.P - s.target;  // g(A) = <exp(-A tau)> - F
-  const double g1 = -tot[1] / s.P;           // g'(A)
-  const double g2 = tot[2] / s.P;            // g''(A)
+// One safeguarded Halley step for g, g' = g1, g'' = g2 at s.A, narrowing the
+// bracket; sets s.A and s.step = |A_new - A_old| / A_new.
+__device__ __forceinline__ void halley(NormState &s, double g, double g1, double g2) {
   double An = s.A;
-  bool conv = false;
-  if (g == 0.0) {
-    conv = true;
-  } else {
+  if (g != 0.0) {
     if (g > 0.0) s.lo = s.A; else s.hi = s.A;
     const double den = 2.0 * g1 * g1 - g * g2;
-    const double halley = (den != 0.0) ? s.A - 2.0 * g * g1 / den : NAN;
+    const double hal = (den != 0.0) ? s.A - 2.0 * g * g1 / den : NAN;
     const double newton = (g1 < 0.0) ? s.A - g / g1 : NAN;
-    if (halley > s.lo && halley < s.hi) An = halley;
+    if (hal > s.lo && hal < s.hi) An = hal;
     else if (newton > s.lo && newton < s.hi) An = newton;
     else if (isfinite(s.hi)) An = 0.5 * (s.lo + s.hi);
     else An = 2.0 * s.A;
-    // Halley converges cubically: once a step is below kNormAcceptStep of A
-    // the iterate it produces is within ~K 1e-15 of the root (K, the ratio of
-    // successive errors to the cube, is below 0.1 on lognormal-field tau),
-    // so it is accepted without another pass.
-    conv = fabs(An - s.A) <= kNormAcceptStep * An;
   }
+  s.step = (g == 0.0) ? 0.0 : fabs(An - s.A) / An;
   s.A = An;
   s.iter += 1;
-  if (conv) {
-    // the approach used FP32 exponentials: finish with exact FP64 moments.
-    // Signs of g seen in the approach can be wrong within its ~1e-7 error,
-    // so the exact phase starts from an open bracket.
-    if (s.exact) {
-      s.done = 1;
-    } else {
-      s.exact = 1;
-      s.lo = 0.0;
-      s.hi = INFINITY;
+}
+
+// The sample: pixel floor(k P / N) for k < N = min(P, kSampleN), gathered by
+// many workgroups into a contiguous buffer (one workgroup pulling 16384
+// scattered cache lines alone would take tens of microseconds).
+__global__ __launch_bounds__(kGatherThreads) void norm_gather_kernel(
+    const float *__restrict__ tau, int64_t P, float *__restrict__ sample) {
+  const int64_t N = P < kSampleN ? P : kSampleN;
+  const int64_t k = (int64_t)blockIdx.x * kGatherThreads + threadIdx.x;
+  if (k < N) sample[k] = tau[(k * P) / N];
+}
+
+// Root of the sample's g: one workgroup of four waves, the sample in LDS.
+// Leaves the state for the full passes (FP32 phase, open bracket, no moments
+// yet).
+__global__ __launch_bounds__(kSampleThreads) void norm_sample_kernel(
+    const float *__restrict__ sample, int64_t P, double target, NormState *st_out) {
+  __shared__ double sh[3 * kSampleWaves];
+  __shared__ float4 xs[kSampleN / 4];
+  const int64_t N = P < kSampleN ? P : kSampleN;
+  double v[3] = {0.0, 0.0, 0.0};  // sum tau, #zeros, #invalid over the sample
+  constexpr int R = kSampleN / 4 / kSampleThreads;  // float4 per thread
+  float4 q[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j)  // every read in flight at once
+    q[j] = reinterpret_cast<const float4 *>(sample)[threadIdx.x + j * kSampleThreads];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int k4 = threadIdx.x + j * kSampleThreads;
+    float t[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool in = 4 * (int64_t)k4 + c < N;  // slots past N hold tau = 0
+      const bool bad = in && (!(t[c] >= 0.f) || !isfinite(t[c]));
+      t[c] = (in && !bad) ? t[c] : 0.f;
+      v[0] += (double)t[c];
+      v[1] += (in && !bad && t[c] == 0.f) ? 1.0 : 0.0;
+      v[2] += bad ? 1.0 : 0.0;
     }
+    xs[k4] = make_float4(t[0], t[1], t[2], t[3]);
+  }
+  block_sum<3, kSampleWaves>(v, sh);  // its barriers publish xs
+  NormState s;
+  s.P = (double)P;
+  s.Ps = (double)N;
+  s.target = target;
+  s.step = INFINITY;
+  s.iter = 0;
+  s.done = 0;
+  s.status = 0;
+  s.phase = kNormPhaseFP32;
+  s.pending = 1;
+  s.buf = 0;
+  s.nparts = 0;
+  s.lo = 0.0;
+  s.hi = INFINITY;
+  const double mean = v[0] / s.Ps;
+  s.A = (mean > 0.0) ? -log(target) / mean : 1.0;
+  // iterate only if the sample is valid and has a root; otherwise the full
+  // passes start from A0 and settle the status
+  if (v[2] == 0.0 && v[1] / s.Ps < target && mean > 0.0) {
+    const double pad = (double)(kSampleN - N);
+    for (int it = 0; it < kSampleIters; ++it) {
+      const float Al = (float)(s.A * kLog2e);
+      float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+      for (int k4 = threadIdx.x; k4 < kSampleN / 4; k4 += kSampleThreads) {
+        const float4 q = xs[k4];
+        const float t[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float e = __builtin_amdgcn_exp2f(-(Al * t[c]));
+          e0 += e;
+          e1 = __builtin_fmaf(t[c], e, e1);
+          e2 = __builtin_fmaf(t[c] * t[c], e, e2);
+        }
+      }
+      double m[3] = {(double)e0, (double)e1, (double)e2};
+      block_sum<3, kSampleWaves>(m, sh);
+      const double g = (m[0] - pad) / s.Ps - target;
+      halley(s, g, -m[1] / s.Ps, m[2] / s.Ps);
+      if (s.step <= kSampleTol) break;
+    }
+  }
+  s.lo = 0.0;
+  s.hi = INFINITY;
+  if (threadIdx.x == 0) *st_out = s;
+}
+
+// One step from full-pass moments (with the domain and root-existence checks
+// on the counts), and the phase change.
+__device__ NormState norm_step(NormState s, const double (&tot)[kNormQ]) {
+  if (tot[4] > 0.0) {
+    s.done = 1;
+    s.status |= LYAF_STATUS_DOMAIN;
+    return s;
+  }
+  if (!(tot[3] / s.P < s.target)) {
+    s.done = 1;
+    s.status |= LYAF_STATUS_NOROOT;
+    return s;
+  }
+  halley(s, tot[0] / s.P - s.target, -tot[1] / s.P, tot[2] / s.P);
+  // a step below kNormAcceptStep of A leaves an iterate within ~K 1e-15 of
+  // the root, accepted without another pass.  The FP32 phase hands over with
+  // an open bracket: the signs of g it saw carry the FP32 error.
+  if (s.phase == kNormPhaseExact) {
+    if (s.step <= kNormAcceptStep) s.done = 1;
+  } else if (s.step <= kFP32Accept) {
+    s.phase = kNormPhaseExact;
+    s.lo = 0.0;
+    s.hi = INFINITY;
   }
   return s;
 }
 
-// Pass k >= 1.  Every workgroup sums the previous pass's partials in the same
-// fixed order and takes the same step, so no update kernel and no
-// device-scope fence are needed; workgroup 0 records the state.  Then, unless
-// the iteration has finished, S_k = sum tau^k exp(-A tau), k = 0..2, at the
-// new A, per workgroup.
-__global__ __launch_bounds__(kNormThreads) void norm_pass_kernel(
-    int pass, const float *__restrict__ tau, int64_t P, double target,
-    const double *__restrict__ part_in, double *__restrict__ part_out,
-    const NormState *st_prev, NormState *st_out, uint32_t *status) {
-  __shared__ double sh[16];
+// A full pass.  Every workgroup reads the state the previous kernel left,
+// sums the previous pass's partials in the same fixed order and takes the
+// same step; workgroup 0 records the result.  Then S0..S2 at the new A (FP32
+// or FP64 exponentials by phase) and the counts, per workgroup.
+__global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
+    const float *__restrict__ tau, int64_t P, double *partials, const NormState *st_prev,
+    NormState *st_out, uint32_t *status) {
+  __shared__ double sh[kNormQ * kPassWaves];
   __shared__ NormState shs;
-  if (threadIdx.x == 0) shs = (pass == 1) ? NormState{} : *st_prev;
+  if (threadIdx.x == 0) shs = *st_prev;
   __syncthreads();
-  if (pass > 1 && shs.done) {  // finished in an earlier pass
-    if (blockIdx.x == 0 && threadIdx.x == 0) *st_out = shs;
+  NormState s = shs;
+  if (s.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st_out = s;
     return;
   }
-  double tot[3];
-  reduce_partials<3>(part_in, gridDim.x, tot, sh);
-  if (threadIdx.x == 0) {
-    const NormState s = (pass == 1) ? norm_start(tot, (double)P, target) : norm_step(shs, tot);
-    shs = s;
-    if (blockIdx.x == 0) {
-      *st_out = s;
-      if (pass == 1 && s.status) atomicOr(status, (uint32_t)s.status);
+  if (!s.pending) {
+    double tot[kNormQ];
+    reduce_partials<kNormQ, kPassWaves>(partials + s.buf * kPartStride * kMaxPartialBlocks,
+                                        s.nparts, tot, sh);
+    if (threadIdx.x == 0) shs = norm_step(s, tot);
+    __syncthreads();
+    s = shs;
+    if (s.done) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *st_out = s;
+        if (s.status) atomicOr(status, (uint32_t)s.status);
+      }
+      return;
     }
   }
-  __syncthreads();
-  if (shs.done) return;
-  const double A = shs.A;
-  const double Al = shs.A * kLog2e;
-  const bool exact = shs.exact != 0;
-  double v[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
-  // two accumulator sets (elements alternate) halve the FP64 add chain
-  auto add2 = [&](double t, double (&a)[3]) {
-    const double e = exact ? exp_neg(A * t) : exp_neg_fast(Al * t);
-    const double te = t * e;
-    a[0] += e;
-    a[1] += te;
-    a[2] = fma(te, t, a[2]);
+  const int out_buf = 1 - s.buf;
+  const bool aligned = (reinterpret_cast<uintptr_t>(tau) & 15) == 0;
+  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P4 = P >> 2;  // whole groups of four pixels; the tail below
+  double m[kNormQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int nz = 0, nbad = 0;
+  auto counts = [&](float t) {
+    nz += (t == 0.f);
+    nbad += (!(t >= 0.f) || !isfinite(t));
   };
-  auto add = [&](double t) { add2(t, v); };
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t done_to = 0;
-  if ((reinterpret_cast<uintptr_t>(tau) & 15) == 0) {
-    const int64_t P4 = P >> 2;
-    const float4 *t4 = reinterpret_cast<const float4 *>(tau);
-    int64_t p = base;
-    for (; p + stride < P4; p += 2 * stride) {  // two loads in flight
-      const float4 qa = t4[p], qb = t4[p + stride];
-      add2(qa.x, v); add2(qa.y, u); add2(qa.z, v); add2(qa.w, u);
-      add2(qb.x, v); add2(qb.y, u); add2(qb.z, v); add2(qb.w, u);
+  auto group = [&](int64_t i) {  // pixels 4i .. 4i+3
+    if (aligned) return reinterpret_cast<const float4 *>(tau)[i];
+    return make_float4(tau[4 * i], tau[4 * i + 1], tau[4 * i + 2], tau[4 * i + 3]);
+  };
+  const int64_t tail = P - 4 * P4;  // 0..3 pixels, one per thread of the first threads
+  if (s.phase == kNormPhaseFP32) {
+    const float Al = (float)(s.A * kLog2e);
+    float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+    auto px = [&](float t) {
+      const float e = __builtin_amdgcn_exp2f(-(Al * t));
+      e0 += e;
+      e1 = __builtin_fmaf(t, e, e1);
+      e2 = __builtin_fmaf(t * t, e, e2);
+      counts(t);
+    };
+    for (int64_t i = gtid; i < P4; i += nthr) {
+      const float4 t = group(i);
+      px(t.x);
+      px(t.y);
+      px(t.z);
+      px(t.w);
+      m[0] += (double)e0;  // FP32 sums of four terms, then FP64
+      m[1] += (double)e1;
+      m[2] += (double)e2;
+      e0 = e1 = e2 = 0.f;
     }
-    for (; p < P4; p += stride) {
-      const float4 qa = t4[p];
-      add2(qa.x, v); add2(qa.y, u); add2(qa.z, v); add2(qa.w, u);
+    if (gtid < tail) {
+      px(tau[4 * P4 + gtid]);
+      m[0] += (double)e0;
+      m[1] += (double)e1;
+      m[2] += (double)e2;
     }
-    done_to = P4 << 2;
+  } else {
+    __shared__ double tab[64];  // 2^(-j/64)
+    if (threadIdx.x < 64) tab[threadIdx.x] = exp_neg(threadIdx.x * (kLn2 / 64.0));
+    __syncthreads();
+    const double A = s.A;
+    auto px = [&](float tf) {
+      const double t = (double)tf;
+      const double e = exp_neg_tab(A * t, tab);
+      const double te = t * e;
+      m[0] += e;
+      m[1] += te;
+      m[2] = fma(te, t, m[2]);
+      counts(tf);
+    };
+    for (int64_t i = gtid; i < P4; i += nthr) {
+      const float4 t = group(i);
+      px(t.x);
+      px(t.y);
+      px(t.z);
+      px(t.w);
+    }
+    if (gtid < tail) px(tau[4 * P4 + gtid]);
   }
-  for (int64_t p = done_to + base; p < P; p += stride) add((double)tau[p]);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) v[k] += u[k];
-  block_sum<3>(v, sh);
+  m[3] = (double)nz;
+  m[4] = (double)nbad;
+  block_sum<kNormQ, kPassWaves>(m, sh);
+  double *out = partials + out_buf * kPartStride * kMaxPartialBlocks;
   if (threadIdx.x == 0) {
-    part_out[blockIdx.x * 4 + 0] = v[0];
-    part_out[blockIdx.x * 4 + 1] = v[1];
-    part_out[blockIdx.x * 4 + 2] = v[2];
+#pragma unroll
+    for (int k = 0; k < kNormQ; ++k) out[blockIdx.x * kPartStride + k] = m[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.pending = 0;
+    s.buf = out_buf;
+    s.nparts = gridDim.x;
+    *st_out = s;
   }
 }
 
 // Last step (from the last pass's moments unless already converged), then
 // tau' = A tau and F = exp(-tau').
 __global__ __launch_bounds__(kNormThreads) void norm_finalise_kernel(
-    float *__restrict__ tau, float *__restrict__ F, int64_t P, int nparts,
-    const double *__restrict__ part_in, const NormState *st_prev, NormState *st_out,
-    double *A_dev, uint32_t *status) {
-  __shared__ double sh[16];
+    float *__restrict__ tau, float *__restrict__ F, int64_t P, const double *partials,
+    const NormState *st_prev, NormState *st_out, double *A_dev, uint32_t *status) {
+  __shared__ double sh[kNormQ * kNormWaves];
   __shared__ NormState shs;
   if (threadIdx.x == 0) shs = *st_prev;
   __syncthreads();
-  if (!shs.done) {  // one more step from the last pass's moments
-    double tot[3];
-    reduce_partials<3>(part_in, nparts, tot, sh);
-    if (threadIdx.x == 0) {
-      NormState s = norm_step(shs, tot);
-      // accepted if the step was small (then norm_step either finished or
-      // moved to the exact phase); otherwise the cap on passes was hit
-      const bool accepted = s.done || s.exact != shs.exact;
-      s.done = 1;
-      if (!accepted) s.status |= LYAF_STATUS_NOCONV;
-      shs = s;
+  if (!shs.done) {
+    if (shs.pending) {  // no moments at A: the cap on passes was hit
+      if (threadIdx.x == 0) {
+        shs.done = 1;
+        shs.status |= LYAF_STATUS_NOCONV;
+      }
+    } else {  // one more step from the last pass's moments
+      double tot[kNormQ];
+      reduce_partials<kNormQ, kNormWaves>(partials + shs.buf * kPartStride * kMaxPartialBlocks,
+                                          shs.nparts, tot, sh);
+      if (threadIdx.x == 0) {
+        NormState s = norm_step(shs, tot);
+        // accepted: converged in the exact phase, or a domain / no-root
+        // verdict, or an FP32-phase step as small as the exact acceptance
+        const bool accepted = s.done || s.step <= kNormAcceptStep;
+        s.done = 1;
+        if (!accepted) s.status |= LYAF_STATUS_NOCONV;
+        shs = s;
+      }
     }
     __syncthreads();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *st_out = shs;
     *A_dev = shs.A;
-    if (shs.status & LYAF_STATUS_NOCONV) atomicOr(status, (uint32_t)LYAF_STATUS_NOCONV);
+    if (shs.status) atomicOr(status, (uint32_t)shs.status);
   }
   const double A = shs.A;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
-    const float ts = (float)(A * (double)tau[p]);
-    tau[p] = ts;
-    if (F) F[p] = expf(-ts);
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((reinterpret_cast<uintptr_t>(tau) & 15) == 0 &&
+      (F == nullptr || (reinterpret_cast<uintptr_t>(F) & 15) == 0)) {
+    const int64_t P4 = P >> 2;
+    float4 *t4 = reinterpret_cast<float4 *>(tau);
+    float4 *f4 = reinterpret_cast<float4 *>(F);
+    for (int64_t p = base; p < P4; p += stride) {
+      const float4 t = t4[p];
+      float4 o;
+      o.x = (float)(A * (double)t.x);
+      o.y = (float)(A * (double)t.y);
+      o.z = (float)(A * (double)t.z);
+      o.w = (float)(A * (double)t.w);
+      t4[p] = o;
+      if (F) f4[p] = make_float4(expf(-o.x), expf(-o.y), expf(-o.z), expf(-o.w));
+    }
+    for (int64_t p = (P4 << 2) + base; p < P; p += stride) {
+      const float ts = (float)(A * (double)tau[p]);
+      tau[p] = ts;
+      if (F) F[p] = expf(-ts);
+    }
+  } else {
+    for (int64_t p = base; p < P; p += stride) {
+      const float ts = (float)(A * (double)tau[p]);
+      tau[p] = ts;
+      if (F) F[p] = expf(-ts);
+    }
   }
 }
 
-static int norm_grid(int64_t P) {
-  int64_t g = (P + kNormThreads * 16 - 1) / (kNormThreads * 16);
-  if (g < 1) g = 1;
-  if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
-  return (int)g;
+static int norm_grid(int64_t pixels) {  // backward reductions
+  int64_t g = (pixels + kNormThreads * 16 - 1) / (kNormThreads * 16);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxPartialBlocks));
 }
 
 hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F, double *A_dev,
                        Workspace &ws, hipStream_t st) {
-  const int grid = norm_grid(n_pix);
-  double *part[2] = {ws.partials, ws.partials + 4 * kMaxPartialBlocks};
-  hipLaunchKernelGGL(norm_init_kernel, dim3(grid), dim3(kNormThreads), 0, st, tau, n_pix,
-                     part[0]);
-  for (int k = 1; k <= kNormMaxIter; ++k)
-    hipLaunchKernelGGL(norm_pass_kernel, dim3(grid), dim3(kNormThreads), 0, st, k, tau, n_pix,
-                       target_F, part[(k - 1) & 1], part[k & 1], ws.norm + (k - 1),
-                       ws.norm + k, ws.status);
-  const int fgrid = (int)std::min<int64_t>((n_pix + 2047) / 2048, 2048);
+  int64_t g = (n_pix + kPassThreads * 16 - 1) / (kPassThreads * 16);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxPartialBlocks));
+  float *sample = reinterpret_cast<float *>(ws.partials + 2 * kPartStride * kMaxPartialBlocks);
+  hipLaunchKernelGGL(norm_gather_kernel, dim3(kSampleN / kGatherThreads), dim3(kGatherThreads),
+                     0, st, tau, n_pix, sample);
+  hipLaunchKernelGGL(norm_sample_kernel, dim3(1), dim3(kSampleThreads), 0, st, sample, n_pix,
+                     target_F, ws.norm);
+  for (int k = 0; k < kNormPasses; ++k)
+    hipLaunchKernelGGL(norm_pass_kernel, dim3(grid), dim3(kPassThreads), 0, st, tau, n_pix,
+                       ws.partials, ws.norm + k, ws.norm + k + 1, ws.status);
+  const int fgrid = (int)std::min<int64_t>((n_pix + 4095) / 4096, 2048);
   hipLaunchKernelGGL(norm_finalise_kernel, dim3(std::max(fgrid, 1)), dim3(kNormThreads), 0, st,
-                     tau, F, n_pix, grid, part[kNormMaxIter & 1], ws.norm + kNormMaxIter,
-                     ws.norm + kNormMaxIter + 1, A_dev, ws.status);
+                     tau, F, n_pix, ws.partials, ws.norm + kNormPasses,
+                     ws.norm + kNormPasses + 1, A_dev, ws.status);
   return hipGetLastError();
 }
 
@@ -347,10 +497,10 @@ __global__ __launch_bounds__(kNormThreads) void normbw_reduce_kernel(
     v[0] += (double)G * (double)tau[p];
     v[1] += (double)Fp * (double)tau[p];
   }
-  block_sum<2>(v, sh);
+  block_sum<2, kNormWaves>(v, sh);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x * 4 + 0] = v[0];
-    partials[blockIdx.x * 4 + 1] = v[1];
+    partials[blockIdx.x * kPartStride + 0] = v[0];
+    partials[blockIdx.x * kPartStride + 1] = v[1];
   }
 }
 
@@ -359,7 +509,7 @@ __global__ __launch_bounds__(kNormThreads) void normbw_ratio_kernel(int nblocks,
                                                                     double *ratio) {
   __shared__ double sh[16];
   double tot[2];
-  reduce_partials<2>(partials, nblocks, tot, sh);
+  reduce_partials<2, kNormWaves>(partials, nblocks, tot, sh);
   if (threadIdx.x == 0) *ratio = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;
 }
 
