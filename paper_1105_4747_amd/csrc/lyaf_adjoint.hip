@@ -10,12 +10,15 @@
 //   dL/dT0 = sum_j Q_j / T0,   dL/dgamma = sum_j Q_j ln D_j.
 // The 1.2 is the temperature exponent of w (n_HI ~ T^-0.7 over b ~ T^0.5).
 //
-// Layout mirrors the forward: one workgroup per 256-source tile; the target
-// gradients g_i within reach are staged in LDS; each lane owns one source and
-// each wave walks the union of its 64 sources' windows, reading g_i as a
-// broadcast.  Short or wide skewers sum over every target with the minimal
-// image chosen per pair.  Per-skewer T0/gamma terms are summed in FP64 per
-// workgroup and then per skewer in a fixed order.
+// One workgroup per 256-source pass; the target gradients g_i within reach are
+// staged in LDS.  Each lane owns one source and walks its own run of targets,
+// four per step, shifted with its source: the run of lane l starts at j_l - H
+// and has NS targets, H and NS uniform over the wave (from the lanes' window
+// bounds), so target minus source is the same on every lane and the four
+// targets of a step share t_k = t_0 + k a (a = dv r).  Short or wide skewers
+// sum over every target with the minimal image chosen per pair.  Per-skewer
+// T0/gamma terms are summed in FP64 per workgroup and then per skewer in a
+// fixed order.
 #include <math.h>
 
 #include "lyaf_internal.h"
@@ -27,6 +30,13 @@ __device__ __forceinline__ float alog2(float x) { return __builtin_amdgcn_logf(x
 
 constexpr int kAdjThreads = 256;
 constexpr int kAdjTile = 256;  // sources per pass of the workgroup (one per thread)
+constexpr int kAdjMargin = 12; // staged targets beyond the reach
+
+__device__ __forceinline__ int adj_wave_max(int x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m));
+  return x;
+}
 static_assert(kTauTile % kAdjTile == 0, "work items hold whole adjoint passes");
 
 // One pass: sources j0 .. j0+255 of skewer s (one per thread).  Adds this
@@ -57,44 +67,51 @@ __device__ void adjoint_pass(const Batch &b, const SkewerConst &K, int64_t off, 
   const float dv = K.dv;
   float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // sums of g E, g E t, g E t^2
 
-  const int e_lo = j0 - R;
-  const int e_hi = j0 + kAdjTile + R;
-  const int cnt = e_hi - e_lo;
+  // staged margin beyond the reach (window bounds are rounded outwards)
+  const int RH = (R + kAdjMargin + 3) & ~3;
+  const int j_end = min(j0 + kAdjTile, n);
+  const int e_lo = j0 - RH;
+  const int cnt = (j_end - j0) + 2 * RH;
   __syncthreads();  // gl is reused across passes
-  if (cnt <= n && cnt <= kChunk) {
-    // windowed: targets e_lo .. e_hi-1 (extended, periodic)
+  if (kAdjTile + 2 * RH + 8 <= kChunk && 2 * RH + 8 <= n) {
+    // windowed: targets e_lo .. e_lo + cnt - 1 (extended, periodic)
     for (int c = threadIdx.x; c < cnt; c += kAdjThreads) {
-      const int e = e_lo + c;
+      const int e = e_lo + c;  // -n <= e < 2n
       const int i = e < 0 ? e + n : (e >= n ? e - n : e);
       gl[c] = g[off + i];
     }
     __syncthreads();
-    // union of this wave's windows, in local target index c = e - e_lo
-    float lo = INFINITY, hi = -INFINITY;
+    // this lane's window in targets: j - Hl .. j + El
+    int Hl = -(1 << 20), El = -(1 << 20);
     if (w > 0.f) {
-      const float cc = (float)j + v * K.inv_dv;
+      const float cc = __builtin_fmaf(v, K.inv_dv, (float)(j - j0));  // line centre
       const float h = b.window_k * bj * K.inv_dv;
-      lo = cc - h - 1.f;
-      hi = cc + h + 1.f;
+      const float lo = fminf(fmaxf(ceilf(cc - h), -8192.f), 8191.f);
+      const float hi = fminf(fmaxf(floorf(cc + h), -8192.f), 8191.f);
+      Hl = (j - j0) - (int)lo;
+      El = (int)hi - (j - j0);
     }
-    for (int m = 32; m >= 1; m >>= 1) {
-      lo = fminf(lo, __shfl_xor(lo, m));
-      hi = fmaxf(hi, __shfl_xor(hi, m));
-    }
-    if (lo <= hi) {
-      const int c_first = max(0, (int)floorf(lo) - e_lo);
-      const int c_last = min(cnt - 1, (int)ceilf(hi) - e_lo);
-      float fd = (float)(e_lo + c_first - j);  // target - source, exact
-      for (int c = c_first; c <= c_last; ++c) {
-        const float gi = gl[c];
-        const float d = __builtin_fmaf(fd, dv, -v);
-        const float t = d * r;
-        const float gE = gi * aexp2(-(t * t));
-        const float gEt = gE * t;
-        S0 += gE;
-        S1 += gEt;
-        S2 = __builtin_fmaf(gEt, t, S2);
-        fd += 1.f;
+    const int H = min(__builtin_amdgcn_readfirstlane(adj_wave_max(Hl)), RH);
+    const int E = __builtin_amdgcn_readfirstlane(adj_wave_max(El));
+    if (E >= -(1 << 19)) {
+      // NS <= H + RH - 8 keeps every read inside the staged targets
+      const int NS = min((H + E + 1 + 3) & ~3, H + RH - 8);
+      const float *gp = gl + (j - j0) + RH - H;  // run start of this lane
+      const float a = dv * r;
+      float fd = (float)(-H);  // target - source at the step's first target, exact
+      for (int st = 0; st < NS; st += 4) {
+        const float gi[4] = {gp[st], gp[st + 1], gp[st + 2], gp[st + 3]};
+        const float t0 = __builtin_fmaf(fd, dv, -v) * r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float t = (k == 0) ? t0 : __builtin_fmaf((float)k, a, t0);
+          const float tt = t * t;
+          const float gE = gi[k] * aexp2(-tt);
+          S0 += gE;
+          S1 = __builtin_fmaf(gE, t, S1);
+          S2 = __builtin_fmaf(gE, tt, S2);
+        }
+        fd += 4.f;
       }
     }
   } else {

@@ -144,6 +144,57 @@ def test_normalise_status_no_root_and_domain():
     assert L.status_read() == 0        # read clears
 
 
+SAMPLE_N = 16384  # pixels the root-find's first stage sees: floor(k P / N), k < N
+
+
+def _sample_blind(rng, P):
+    """tau over P = 4 N pixels with every sampled pixel (k P / N = 4k) zero."""
+    import torch
+    raw = (np.exp(rng.normal(0.0, 1.0, P)) * 0.4).astype(np.float32)
+    raw[::4] = 0.0
+    return raw, torch.from_numpy(raw).to("cuda:0")
+
+
+def test_normalise_sample_sees_only_zeros():
+    """The first stage converges on evenly spaced pixels; here all of them are
+    zero and the signal lies between them.  The passes over every pixel must
+    still reach the root, or say that they did not (NOCONV): never a wrong A
+    with a clean status."""
+    from paper_1105_4747_amd import lyaf as L
+    rng = np.random.default_rng(7)
+    raw, d = _sample_blind(rng, 4 * SAMPLE_N)
+    L.status_read()
+    ts, F, A = gpu_normalise(d, 0.8)
+    st = L.status_read()
+    A_ref, _ = O.mean_flux_A(raw.astype(np.float64), 0.8)
+    print(f"blind sample: A={float(A.cpu()):.12g} ref={A_ref:.12g} status={st}")
+    if st == 0:
+        assert abs(float(A.cpu()) / A_ref - 1) <= A_REL
+    else:
+        assert st == L.STATUS_NOCONV
+
+
+def test_normalise_root_and_domain_checks_cover_unsampled_pixels():
+    """No root, or an invalid value, that only the pixels outside the sample
+    reveal: the full passes report it."""
+    import torch
+    from paper_1105_4747_amd import lyaf as L
+    P = 4 * SAMPLE_N
+    L.status_read()
+    raw = torch.zeros(P, device="cuda:0")
+    raw[::4] = 1.0                      # the sample alone has a root for F = 0.7
+    gpu_normalise(raw, 0.7)             # 75% of all pixels transmit fully: none
+    assert L.status_read() == L.STATUS_NOROOT
+    rng = np.random.default_rng(8)
+    good = torch.from_numpy((np.exp(rng.normal(0.0, 1.0, P)) * 0.4).astype(np.float32))
+    good = good.to("cuda:0")
+    gpu_normalise(good, 0.7)
+    assert L.status_read() == 0
+    good[4 * 1000 + 1] = float("nan")   # not a sampled pixel
+    gpu_normalise(good, 0.7)
+    assert L.status_read() & L.STATUS_DOMAIN
+
+
 def test_tau_status_domain():
     from paper_1105_4747_amd import lyaf as L
     w = fields.small_workload(n_skewers=2, n_pix=64, seed=2)
