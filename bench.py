@@ -13,8 +13,12 @@ Prints one JSON line.  ``value`` is skewer-pixels per second of tau + F.
 pairs inside the +-k b window (counted exactly from the inputs) times 7
 operations per pair (6 FP32 flops and one exp2), divided by the stage's
 average duration measured with HIP events on its stream, against the FP32
-vector peak of 157.3 TFLOP/s.  ``cpu_baseline`` is the FP64 oracle (full sum
-+ root-find) on a bounded sample of the same workload on the host cores.
+vector peak of 157.3 TFLOP/s; beside it, the pair rate against the pair-rate
+roofline 1 / (c_exp + 4 c_valu) from the FMA and exp2 rates measured on the
+device in the same run (libpeaks).  ``detail.adjoint`` times the hand-written
+adjoint (lyaf_tau_backward) on the 4096 x 2048 workload.  ``cpu_baseline`` is
+the FP64 oracle (full sum + root-find) on a bounded sample of the same
+workload on the host cores.
 """
 from __future__ import annotations
 
@@ -60,6 +64,32 @@ def algorithmic_pairs(w) -> float:
         cnt = np.minimum(np.maximum(cnt, 0), lens[sk])
         total += float(np.where(d > 0, cnt, 0).sum())
     return total
+
+
+def adjoint_section(L, torch, dev, fields, timed, reps, peak):
+    """The hand-written adjoint on the 4096 x 2048 workload: lyaf_tau_backward
+    (reach pass, adjoint pair kernel, per-skewer FP64 sums) for a random
+    cotangent, and the forward tau stage for comparison; HIP events."""
+    w = fields.config5()
+    print(f"bench: adjoint {w.name}", file=sys.stderr, flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = [t(x) for x in (w.delta, w.vpec, w.dv, w.T0, w.gamma)]
+    P = w.n_pix
+    raw = torch.empty(P, device=dev, dtype=torch.float32)
+    g = torch.randn(P, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    gd, gv = torch.empty_like(raw), torch.empty_like(raw)
+    gT = torch.empty(w.n_skewers, device=dev, dtype=torch.float64)
+    gg = torch.empty_like(gT)
+    t_fwd = timed(lambda: L.tau(*d, w.offsets, raw, window_k=w.window_k), reps)
+    t_bwd = timed(lambda: L.tau_backward(*d, w.offsets, g, gd, gv, gT, gg,
+                                         window_k=w.window_k), reps)
+    pairs = algorithmic_pairs(w)
+    out = {"workload": w.name, "n_pix": P, "tau_backward_ms": round(t_bwd * 1e3, 4),
+           "tau_forward_ms": round(t_fwd * 1e3, 4), "pairs_per_px": round(pairs / P, 2),
+           "adjoint_pair_rate_per_s": pairs / t_bwd, "px_per_s": P / t_bwd}
+    if peak is not None:
+        out["adjoint_pair_frac"] = round(pairs / t_bwd / peak["pair_peak_per_s"], 4)
+    return out
 
 
 def batched_section(L, torch, dev, fields, timed, reps):
@@ -163,6 +193,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint section (4096 x 2048), for profiling")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"])
     ap.add_argument("--tau-only", action="store_true",
                     help="only run the tau stage (reach + windowed kernel) K times, for profiling")
@@ -196,6 +230,26 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_per_launch": 2 * src.numel() * 4}))
         return
+    if args.adjoint_only:
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+        def timed(fn, n):
+            fn()
+            ev0.record()
+            for _ in range(n):
+                fn()
+            ev1.record()
+            ev1.synchronize()
+            return ev0.elapsed_time(ev1) / n * 1e-3
+
+        print(json.dumps({"adjoint_only": True, **adjoint_section(
+            L, torch, dev, fields, timed, max(args.steps, 1), None)}), flush=True)
+        return
+    peak = None
+    if not args.no_peaks and not args.tau_only:
+        from paper_1105_4747_amd import peaks as PK
+        peak = PK.measure()
+        print(f"bench: peaks {json.dumps(peak)}", file=sys.stderr, flush=True)
     w = getattr(fields, args.workload)()
     print(f"bench: workload {w.name}, P={w.n_pix}", file=sys.stderr, flush=True)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -282,6 +336,9 @@ def main():
                 "kernel_ms": round(t_tau * 1e3, 4),
                 "pairs_per_launch": pairs, "pairs_per_px": round(pairs / P, 3),
                 "pair_rate_per_s": pairs / t_tau, "ops_per_pair": OPS_PER_PAIR}
+    if peak is not None:
+        roofline["pair_peak_per_s"] = peak["pair_peak_per_s"]
+        roofline["pair_frac"] = round(pairs / t_tau / peak["pair_peak_per_s"], 4)
     extra = {"plan": info, "tau_stage_ms": round(t_tau * 1e3, 4),
              "normalise_stage_ms": round(t_norm * 1e3, 4),
              "eager_step_ms": round(t_eager * 1e3, 4)}
@@ -297,6 +354,13 @@ def main():
 
     if not args.no_batched:
         extra["batched"] = batched_section(L, torch, dev, fields, timed, reps)
+    if not args.no_adjoint:
+        extra["adjoint"] = adjoint_section(L, torch, dev, fields, timed, reps, peak)
+    if peak is not None:
+        extra["peaks"] = {k: peak[k] for k in ("fma_lane_ops_per_s", "pair_per_s_exp",
+                                               "pair_per_s_noexp", "c_exp_s", "c_valu_s",
+                                               "pair_peak_per_s", "copy_bytes_per_s")}
+        extra["peaks"]["exp_cost_in_fma_slots"] = round(peak["c_exp_s"] / peak["c_valu_s"], 3)
     plan.close()
 
     cpu = None

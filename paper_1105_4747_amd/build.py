@@ -1,4 +1,6 @@
-"""Build liblyaf.so for gfx950 with hipcc (in-tree, next to this file)."""
+"""Build liblyaf.so (the library) and libpeaks.so (the rate microbenchmarks
+the benchmark reports against) for gfx950 with hipcc, in-tree next to this
+file."""
 from __future__ import annotations
 
 import glob
@@ -12,6 +14,8 @@ LIB = os.path.join(HERE, "liblyaf.so")
 SOURCES = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 HEADERS = sorted(glob.glob(os.path.join(HERE, "csrc", "*.h"))) + [
     os.path.join(ROOT, "include", "lyaf.h")]
+PEAKS_LIB = os.path.join(HERE, "libpeaks.so")
+PEAKS_SOURCES = [os.path.join(HERE, "peaks", "lyaf_peaks.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -31,9 +35,9 @@ def needs_build() -> bool:
     return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS)
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+def _hipcc(out: str, sources, verbose: bool) -> str:
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,8 +47,13 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(PEAKS_LIB, PEAKS_SOURCES, verbose)
+    return _hipcc(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

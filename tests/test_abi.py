@@ -147,3 +147,18 @@ def test_library_does_not_link_the_oracle():
                 assert "oracle" not in txt.lower(), f"{fn} mentions the oracle"
     so = open(L.library_path(), "rb").read()
     assert b"oracle_" not in so
+
+
+def test_peaks_library_exports_and_rejects_null():
+    """libpeaks.so (the benchmark's rate microbenchmarks) exports what
+    include/lyaf_peaks.h declares; a null output is rejected before any
+    device call."""
+    from paper_1105_4747_amd import peaks
+    src = open(os.path.join(ROOT, "include", "lyaf_peaks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"^\s*int\s+(lyaf_\w+)\s*\(", src, re.M)))
+    lib = peaks.load()
+    assert names == sorted(peaks.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n)
+    assert lib.lyaf_peaks_measure(None, None) == -1
