@@ -428,7 +428,7 @@ constexpr int kSkewM = 4;                  // targets per lane
 constexpr int kSkewSpan = kWave * kSkewM;  // targets per wave
 constexpr int kSkewFold = 16;              // Kahan fold period (terms per run)
 constexpr int kSkewMargin = 12;            // staged sources beyond the reach
-constexpr int kSkewGroup = 8;              // sources per window-bounds group
+constexpr int kSkewGroup = 4;              // sources per window-bounds group
 // Target-minus-source offsets as exact floats, read from LDS four at a time
 // (one broadcast read per block of four steps instead of a VALU decrement per
 // step): entry k holds kFdTop - k.  A lane run covers offsets H4 .. H4 - NS + 1
@@ -481,8 +481,8 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   // ---- stage extended indices e_lo .. i_end + RH - 1 (position c = e - e_lo).
   // A thread issues its global reads in rounds of 8 ahead of the arithmetic
   // of the round.  The
-  // window bounds of every group of 8 positions (lowest ceil(lo), highest
-  // floor(hi)) meet in a DPP reduction over the 8 lanes that hold them.
+  // window bounds of every group of 4 positions (lowest ceil(lo), highest
+  // floor(hi)) meet in a DPP reduction over the 4 lanes that hold them.
   constexpr int SIT = 8;  // positions per thread per round of reads
   const int e_lo = i0 - RH;
   const int cnt = (i_end - i0) + 2 * RH;
