@@ -64,6 +64,10 @@ __device__ void adjoint_pass(const Batch &b, const SkewerConst &K, int64_t off, 
       bj = K.B * aexp2(0.5f * x);
     }
   }
+  // an invalid density sets the sticky domain bit (the reach pass may not
+  // have read Delta)
+  if (__any(valid && (!(delta >= 0.f) || !isfinite(delta))) && (threadIdx.x & 63) == 0)
+    atomicOr(b.status, LYAF_STATUS_DOMAIN);
   const float dv = K.dv;
   float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // sums of g E, g E t, g E t^2
 

@@ -58,6 +58,14 @@ __device__ __forceinline__ Src source_of(float delta, const SkewerConst &K, floa
   return o;
 }
 
+// Sticky domain bit when any lane of the wave has read an invalid density
+// (negative or not finite).  Every kernel that stages sources checks them: the
+// reach pass reads Delta only when the temperature-density relation needs it.
+__device__ __forceinline__ void flag_bad_delta(const Batch &b, bool bad) {
+  if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(b.status, LYAF_STATUS_DOMAIN);
+}
+__device__ __forceinline__ bool bad_delta(float d) { return !(d >= 0.f) || !isfinite(d); }
+
 template <typename T>
 __device__ __forceinline__ T block_reduce_max(T v, T *sh) {
   for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m));
@@ -98,12 +106,34 @@ __global__ __launch_bounds__(256) void reach_kernel(Batch b) {
     K.n = n;
   }
   float mr = 0.f;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const float d = b.delta[off + j], v = b.vpec[off + j];
-    if (!(d >= 0.f) || !isfinite(d) || !isfinite(v)) bad = 1;
-    if (d > 0.f) {
-      const Src o = source_of(d, K, b.pivot);
-      mr = fmaxf(mr, (fabsf(v) + b.window_k * o.b) * K.inv_dv);
+  if (!bad && K.gm1 >= 0.f && isfinite(b.pivot)) {
+    // T rises with Delta up to the pivot, so b <= beta sqrt(T0 pivot^(gamma-1))
+    // for every source: only the velocities are read.  The kernels that stage
+    // the sources check Delta.
+    const float b_piv =
+        (float)(kBeta * sqrt((double)T0 * pow((double)b.pivot, (double)K.gm1)) * (1.0 + 1e-6));
+    float mv = 0.f;
+    int j = threadIdx.x;
+    for (; j + 3 * (int)blockDim.x < n; j += 4 * (int)blockDim.x) {  // four reads in flight
+      const float v0 = b.vpec[off + j], v1 = b.vpec[off + j + blockDim.x];
+      const float v2 = b.vpec[off + j + 2 * blockDim.x], v3 = b.vpec[off + j + 3 * blockDim.x];
+      mv = fmaxf(mv, fmaxf(fmaxf(fabsf(v0), fabsf(v1)), fmaxf(fabsf(v2), fabsf(v3))));
+      if (!isfinite(v0 + v1 + v2 + v3)) bad = 1;
+    }
+    for (; j < n; j += blockDim.x) {
+      const float v = b.vpec[off + j];
+      mv = fmaxf(mv, fabsf(v));
+      if (!isfinite(v)) bad = 1;
+    }
+    if (n > 0) mr = (mv + b.window_k * b_piv) * K.inv_dv;
+  } else {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const float d = b.delta[off + j], v = b.vpec[off + j];
+      if (!(d >= 0.f) || !isfinite(d) || !isfinite(v)) bad = 1;
+      if (d > 0.f) {
+        const Src o = source_of(d, K, b.pivot);
+        mr = fmaxf(mr, (fabsf(v) + b.window_k * o.b) * K.inv_dv);
+      }
     }
   }
   if (bad) atomicOr(shbad, 1);
@@ -138,12 +168,15 @@ __device__ void full_sum_tile(const Batch &b, const SkewerConst &K, int64_t off,
   for (int c0 = 0; c0 < n; c0 += kChunk) {
     const int cnt = min(kChunk, n - c0);
     __syncthreads();
+    bool bad = false;
     for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
       const int j = c0 + c;
       const float d = b.delta[off + j], v = b.vpec[off + j];
+      bad |= bad_delta(d);
       const Src o = source_of(d, K, b.pivot);
       rec[c] = make_float4(o.w, o.r, v, 0.f);
     }
+    flag_bad_delta(b, bad);
     __syncthreads();
     float fd = (float)(i - c0);
     for (int c = 0; c < cnt; ++c) {
@@ -256,10 +289,12 @@ __device__ __forceinline__ void tau_tile(const Batch &b, const int2 item, float 
   }
 
   const float pivot = b.pivot, wk = b.window_k;
+  bool bad = false;
   for (int c = threadIdx.x; c < cnt; c += kTauThreads) {
     const int e = e_lo + c;  // -n < e < 2n in window mode (R < n/2)
     const int j = e < 0 ? e + n : (e >= n ? e - n : e);
     const float d = b.delta[off + j], v = b.vpec[off + j];
+    bad |= bad_delta(d);
     const Src o = source_of(d, K, pivot);
     float lo = INFINITY, hi = -INFINITY;
     if (o.w > 0.f) {
@@ -273,6 +308,7 @@ __device__ __forceinline__ void tau_tile(const Batch &b, const int2 item, float 
     hi = stream_max<G>(hi);
     if ((threadIdx.x & (G - 1)) == 0) bnd[c / G] = make_float2(lo, hi);
   }
+  flag_bad_delta(b, bad);
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -487,6 +523,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   const int e_lo = i0 - RH;
   const int cnt = (i_end - i0) + 2 * RH;
   const float pivot = b.pivot, wk = b.window_k;
+  bool bad = false;
   for (int c0 = 0; c0 < cnt; c0 += SIT * NT) {
     float dd[SIT], vv[SIT];
 #pragma unroll
@@ -505,6 +542,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     for (int u = 0; u < SIT; ++u) {
       if (c0 + u * NT >= cnt) break;
       const int c = c0 + threadIdx.x + u * NT;
+      bad |= (c < cnt) && bad_delta(dd[u]);
       const Src o = source_of(dd[u], K, pivot);
       float flo = 8191.f, fhi = -8192.f;  // no window: meets no target
       if (c < cnt) {
@@ -523,6 +561,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
             (int)(((uint32_t)(int)fhi & 0xFFFFu) | ((uint32_t)(int)flo << 16));
     }
   }
+  flag_bad_delta(b, bad);
   __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
