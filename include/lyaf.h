@@ -155,6 +155,67 @@ int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm,
                       float *grad_vpec, double *grad_T0, double *grad_gamma,
                       void *stream);
 
+/* ---- instrument model: mock observations of the flux ----
+ *
+ * Sections 3.1, 3.2 and 4.2 turn each flux spectrum into a mock observation:
+ * convolution with a Gaussian line-spread function of given FWHM, resampling
+ * onto coarser bins, and Gaussian noise of given S/N (the BOSS-like spectra of
+ * Section 3.2 are also restricted to the quasar's Lya-Lyb path minus 3000 km/s,
+ * which lyaf_lya_lyb_path_kms gives).  For skewer s of N pixels of width dv:
+ *
+ *   Fc_i   = sum_m c_m F_{(i-m) mod N},  c_m = g(m dv) / sum_m' g(m' dv),
+ *            g(d) = exp(-(d / b_L)^2),  b_L = FWHM / (2 sqrt(ln 2)),
+ *            over the taps |m dv| <= window_k b_L (the whole box at minimal
+ *            images when that reaches half the box or window_k = 0);
+ *   Fbin_k = average over [v_start + k bin, v_start + (k+1) bin) (periodic) of
+ *            the spectrum that is constant, Fc_i, on pixel i, which covers
+ *            velocities [(i - 1/2) dv, (i + 1/2) dv);
+ *   Fobs_k = Fbin_k + noise_sigma * noise_k.
+ *
+ * The truncation error of the taps is below exp(-window_k^2) of the total
+ * weight (6 gives 2.3e-16).  FWHM = 0 skips the convolution. */
+typedef struct {
+  double fwhm_kms;     /* FWHM of the line-spread function, km/s, finite, >= 0 */
+  double bin_kms;      /* width of an output bin, km/s, finite, > 0 */
+  double v_start_kms;  /* lower edge of every skewer's first bin, km/s, finite */
+  double noise_sigma;  /* noise standard deviation (1/(S/N) in continuum units), >= 0 */
+  double window_k;     /* tap truncation in units of b_L, >= 0; 0 = whole box */
+} lyaf_instrument_params;
+
+/* Mock observation of a batch of flux skewers.
+ *   offsets:     HOST [S+1] int64 pixel offsets, as in lyaf_skewers.
+ *   dv:          DEVICE [S] float pixel widths, km/s (> 0).
+ *   F:           DEVICE [P] float flux.
+ *   out_offsets: HOST [S+1] int64: skewer s yields out_offsets[s+1] -
+ *                out_offsets[s] bins (0 allowed), written to F_obs from
+ *                out_offsets[s].  A skewer with bins needs N > 0 pixels.
+ *   noise:       DEVICE [P_out] float standard-normal draws, read only when
+ *                noise_sigma > 0 (then required); the caller draws them.
+ *   F_obs:       DEVICE [P_out] float, written.
+ * Host-visible errors (EINVAL): NULL pointers, bad offsets, parameters out of
+ * range.  Device-visible (LYAF_STATUS_DOMAIN, skewer skipped): dv <= 0 or not
+ * finite, bins longer than the box (n_out bin > N dv), or a bin wider than 252
+ * pixels. */
+int lyaf_instrument(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
+                    const lyaf_instrument_params *ip, const int64_t *out_offsets,
+                    const float *noise, float *F_obs, void *stream);
+
+/* Adjoint of lyaf_instrument: grad_F = J^T grad_obs for the linear map
+ * F -> Fbin (the noise does not depend on F).  grad_obs: DEVICE [P_out] float;
+ * grad_F: DEVICE [P] float, written (zero for skewers without bins).  Same
+ * arguments and errors as lyaf_instrument (noise_sigma is ignored). */
+int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const float *dv,
+                             const lyaf_instrument_params *ip, const int64_t *out_offsets,
+                             const float *grad_obs, float *grad_F, void *stream);
+
+/* Velocity width of dlambda Angstrom at Lyman alpha observed at redshift z:
+ * c dlambda / (1215.67 A (1 + z)).  At z = 3, 3.63 A is 223.8 km/s (Section
+ * 3.2 prints ~224). */
+double lyaf_angstrom_to_kms(double dlambda_angstrom, double z);
+/* Velocity length of a quasar's Lya-Lyb path, c ln(1215.67 / 1025.72), minus
+ * the proximity zone (Section 3.2: 3000 km/s). */
+double lyaf_lya_lyb_path_kms(double proximity_kms);
+
 /* ---- plans: the whole forward, tuned and captured once, replayed many times ----
  *
  * Section 2.3 applies the same steps to every spectrum of a survey: eq. (6) per

@@ -182,6 +182,109 @@ int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out)
   return LYAF_OK;
 }
 
+// Host mirror of the instrument work list uploaded to a workspace.
+struct HostInsPlan {
+  bool backward = false;
+  std::vector<int64_t> offsets, out_offsets;  // [S+1] each
+  int64_t n_items = 0;
+  int64_t *h_off = nullptr, *h_oo = nullptr;
+  int2 *h_items = nullptr;
+  int64_t h_off_cap = 0, h_oo_cap = 0, h_items_cap = 0;
+};
+std::map<Workspace *, HostInsPlan> g_ins_plans;
+
+int check_ins(int64_t S, const int64_t *offsets, const float *dv,
+              const lyaf_instrument_params *ip, const int64_t *out_offsets, int64_t *P_out,
+              int64_t *Pout_out) {
+  if (!ip || S < 0) return LYAF_EINVAL;
+  if (!(ip->fwhm_kms >= 0.0) || !isfinite(ip->fwhm_kms)) return LYAF_EINVAL;
+  if (!(ip->bin_kms > 0.0) || !isfinite(ip->bin_kms)) return LYAF_EINVAL;
+  if (!isfinite(ip->v_start_kms)) return LYAF_EINVAL;
+  if (!(ip->noise_sigma >= 0.0) || !isfinite(ip->noise_sigma)) return LYAF_EINVAL;
+  if (!(ip->window_k >= 0.0) || !isfinite(ip->window_k)) return LYAF_EINVAL;
+  int64_t P = 0, Po = 0;
+  if (S > 0) {
+    if (!offsets || !out_offsets || !dv) return LYAF_EINVAL;
+    if (offsets[0] != 0 || out_offsets[0] != 0) return LYAF_EINVAL;
+    for (int64_t s = 0; s < S; ++s) {
+      const int64_t n = offsets[s + 1] - offsets[s];
+      const int64_t no = out_offsets[s + 1] - out_offsets[s];
+      if (n < 0 || n > (int64_t(1) << 24) || no < 0) return LYAF_EINVAL;
+      if (no > 0 && n == 0) return LYAF_EINVAL;
+    }
+    P = offsets[S];
+    Po = out_offsets[S];
+  }
+  *P_out = P;
+  *Pout_out = Po;
+  return LYAF_OK;
+}
+
+// Upload the offsets and the (skewer, item) list of the instrument kernels,
+// unless the workspace already holds this exact list.
+int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int64_t *out_offsets,
+                    bool backward, HostInsPlan **out) {
+  HostInsPlan &hp = g_ins_plans[ws];
+  *out = &hp;
+  if (hp.backward == backward && (int64_t)hp.offsets.size() == S + 1 &&
+      memcmp(hp.offsets.data(), offsets, sizeof(int64_t) * (size_t)(S + 1)) == 0 &&
+      memcmp(hp.out_offsets.data(), out_offsets, sizeof(int64_t) * (size_t)(S + 1)) == 0)
+    return LYAF_OK;
+  hipError_t e;
+  // the pinned staging buffers may still feed an earlier copy on this stream
+  if ((e = hipStreamSynchronize(ws->stream)) != hipSuccess) return map_err(e);
+  hp.offsets.clear();
+  int64_t ni = 0;
+  for (int64_t s = 0; s < S; ++s)
+    ni += ins_items_per_skewer(offsets[s + 1] - offsets[s], out_offsets[s + 1] - out_offsets[s],
+                               backward);
+  if (ni > INT32_MAX) return LYAF_EINVAL;
+  if ((e = grow_host(hp.h_off, hp.h_off_cap, S + 1)) != hipSuccess ||
+      (e = grow_host(hp.h_oo, hp.h_oo_cap, S + 1)) != hipSuccess ||
+      (e = grow_host(hp.h_items, hp.h_items_cap, ni)) != hipSuccess ||
+      (e = grow_dev(ws->ins_off, ws->ins_off_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(ws->ins_oo, ws->ins_oo_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(ws->ins_items, ws->ins_items_cap, ni)) != hipSuccess)
+    return map_err(e);
+  memcpy(hp.h_off, offsets, sizeof(int64_t) * (size_t)(S + 1));
+  memcpy(hp.h_oo, out_offsets, sizeof(int64_t) * (size_t)(S + 1));
+  int64_t k = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int c = ins_items_per_skewer(offsets[s + 1] - offsets[s],
+                                       out_offsets[s + 1] - out_offsets[s], backward);
+    for (int t = 0; t < c; ++t) hp.h_items[k++] = make_int2((int)s, t);
+  }
+  if ((e = hipMemcpyAsync(ws->ins_off, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
+                          hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws->ins_oo, hp.h_oo, sizeof(int64_t) * (size_t)(S + 1),
+                          hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
+      (ni > 0 && (e = hipMemcpyAsync(ws->ins_items, hp.h_items, sizeof(int2) * (size_t)ni,
+                                     hipMemcpyHostToDevice, ws->stream)) != hipSuccess))
+    return map_err(e);
+  hp.backward = backward;
+  hp.offsets.assign(offsets, offsets + S + 1);
+  hp.out_offsets.assign(out_offsets, out_offsets + S + 1);
+  hp.n_items = ni;
+  return LYAF_OK;
+}
+
+InsArgs make_ins_args(Workspace *ws, const float *dv, const lyaf_instrument_params *ip) {
+  InsArgs a;
+  a.offsets = ws->ins_off;
+  a.out_offsets = ws->ins_oo;
+  a.dv = dv;
+  a.in = nullptr;
+  a.out = nullptr;
+  a.noise = nullptr;
+  a.fwhm = ip->fwhm_kms;
+  a.bin = ip->bin_kms;
+  a.v_start = ip->v_start_kms;
+  a.sigma = ip->noise_sigma;
+  a.window_k = ip->window_k;
+  a.status = ws->status;
+  return a;
+}
+
 Batch make_batch(const lyaf_skewers *sk, const lyaf_params *prm, Workspace *ws) {
   Batch b;
   b.delta = sk->delta;
@@ -315,6 +418,55 @@ int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm, const floa
   }
   return map_err(launch_tau_adjoint(b, ws->items, hp->n_items, ws->item_base, grad_tau_raw,
                                     grad_delta, grad_vpec, grad_T0, grad_gamma, ws->gpart, st));
+}
+
+int lyaf_instrument(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
+                    const lyaf_instrument_params *ip, const int64_t *out_offsets,
+                    const float *noise, float *F_obs, void *stream) {
+  int64_t P = 0, Po = 0;
+  int rc = check_ins(n_skewers, offsets, dv, ip, out_offsets, &P, &Po);
+  if (rc) return rc;
+  if (Po == 0) return LYAF_OK;
+  if (!F || !F_obs || (ip->noise_sigma > 0.0 && !noise)) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace *ws = nullptr;
+  if ((rc = get_ws(st, &ws))) return rc;
+  HostInsPlan *hp = nullptr;
+  if ((rc = ensure_ins_plan(ws, n_skewers, offsets, out_offsets, false, &hp))) return rc;
+  InsArgs a = make_ins_args(ws, dv, ip);
+  a.in = F;
+  a.out = F_obs;
+  a.noise = ip->noise_sigma > 0.0 ? noise : nullptr;
+  return map_err(launch_instrument(a, ws->ins_items, hp->n_items, false, st));
+}
+
+int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const float *dv,
+                             const lyaf_instrument_params *ip, const int64_t *out_offsets,
+                             const float *grad_obs, float *grad_F, void *stream) {
+  int64_t P = 0, Po = 0;
+  int rc = check_ins(n_skewers, offsets, dv, ip, out_offsets, &P, &Po);
+  if (rc) return rc;
+  if (P == 0) return LYAF_OK;
+  if (!grad_F || (Po > 0 && !grad_obs)) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace *ws = nullptr;
+  if ((rc = get_ws(st, &ws))) return rc;
+  HostInsPlan *hp = nullptr;
+  if ((rc = ensure_ins_plan(ws, n_skewers, offsets, out_offsets, true, &hp))) return rc;
+  InsArgs a = make_ins_args(ws, dv, ip);
+  a.in = grad_obs;
+  a.out = grad_F;
+  return map_err(launch_instrument(a, ws->ins_items, hp->n_items, true, st));
+}
+
+double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {
+  return kSpeedOfLightKms * dlambda_angstrom / (kLymanAlphaAngstrom * (1.0 + z));
+}
+
+double lyaf_lya_lyb_path_kms(double proximity_kms) {
+  return kSpeedOfLightKms * log(kLymanAlphaAngstrom / kLymanBetaAngstrom) - proximity_kms;
 }
 
 int lyaf_status_read(void *stream, uint32_t *device_status) {

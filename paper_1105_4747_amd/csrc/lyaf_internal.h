@@ -75,6 +75,10 @@ struct Workspace {
   int64_t *item_base = nullptr; int64_t ib_cap = 0;    // [S+1] first item of each skewer
   double *gpart = nullptr;     int64_t gpart_cap = 0;  // adjoint per-item FP64 partials
   unsigned int *queue = nullptr;                      // persistent work-queue counter
+  // instrument model: device offsets and work list (host mirror in the API)
+  int64_t *ins_off = nullptr;  int64_t ins_off_cap = 0;
+  int64_t *ins_oo = nullptr;   int64_t ins_oo_cap = 0;
+  int2 *ins_items = nullptr;   int64_t ins_items_cap = 0;
 };
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
@@ -121,6 +125,25 @@ hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F,
 hipError_t launch_norm_backward(int64_t n_pix, const float *tau, const double *A_dev,
                                 const float *gF, const float *gT, int implicit_A,
                                 float *out, Workspace &ws, hipStream_t st);
+// Instrument model (Gaussian line-spread convolution, resampling, noise).
+constexpr int kInsMaxRatio = 252;                         // largest bin width in pixels
+constexpr double kInvTwoSqrtLn2 = 0.60056120439322491;    // b_L = FWHM / (2 sqrt(ln 2))
+constexpr double kSpeedOfLightKms = 299792.458;
+constexpr double kLymanAlphaAngstrom = 1215.67;  // rest wavelengths (vacuum)
+constexpr double kLymanBetaAngstrom = 1025.72;
+struct InsArgs {
+  const int64_t *offsets;      // device [S+1] pixel offsets
+  const int64_t *out_offsets;  // device [S+1] bin offsets
+  const float *dv;             // device [S]
+  const float *in;             // forward: F [P]; backward: grad of the bins [P_out]
+  float *out;                  // forward: bins [P_out]; backward: grad of F [P]
+  const float *noise;          // forward: [P_out] or null
+  double fwhm, bin, v_start, sigma, window_k;
+  uint32_t *status;
+};
+int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward);
+hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items, bool backward,
+                             hipStream_t st);
 hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
                               const int64_t *item_base_dev, const float *g,
                               float *gdelta, float *gvpec, double *gT0,

@@ -40,7 +40,14 @@ def FLAG_SHAPE(v: int) -> int:
 EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_backward",
             "lyaf_tau_backward", "lyaf_status_read", "lyaf_strerror", "lyaf_version",
             "lyaf_plan_create", "lyaf_plan_execute", "lyaf_plan_status", "lyaf_plan_describe",
-            "lyaf_plan_destroy")
+            "lyaf_plan_destroy", "lyaf_instrument", "lyaf_instrument_backward",
+            "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms")
+
+
+class InstrumentParams(ctypes.Structure):
+    _fields_ = [("fwhm_kms", ctypes.c_double), ("bin_kms", ctypes.c_double),
+                ("v_start_kms", ctypes.c_double), ("noise_sigma", ctypes.c_double),
+                ("window_k", ctypes.c_double)]
 
 
 class LyafError(RuntimeError):
@@ -108,6 +115,16 @@ def load():
         lib.lyaf_plan_describe.restype = i32
         lib.lyaf_plan_destroy.argtypes = [vp]
         lib.lyaf_plan_destroy.restype = i32
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        PI = ctypes.POINTER(InstrumentParams)
+        lib.lyaf_instrument.argtypes = [i64, pi64, vp, vp, PI, pi64, vp, vp, vp]
+        lib.lyaf_instrument.restype = i32
+        lib.lyaf_instrument_backward.argtypes = [i64, pi64, vp, PI, pi64, vp, vp, vp]
+        lib.lyaf_instrument_backward.restype = i32
+        lib.lyaf_angstrom_to_kms.argtypes = [dbl, dbl]
+        lib.lyaf_angstrom_to_kms.restype = dbl
+        lib.lyaf_lya_lyb_path_kms.argtypes = [dbl]
+        lib.lyaf_lya_lyb_path_kms.restype = dbl
         _lib = lib
         return lib
 
@@ -189,6 +206,50 @@ def tau_backward(delta, vpec, dv, T0, gamma, offsets, grad_tau_raw, grad_delta, 
                                     _ptr(grad_delta), _ptr(grad_vpec), _ptr(grad_T0),
                                     _ptr(grad_gamma), _stream(stream)),
            "lyaf_tau_backward")
+
+
+def angstrom_to_kms(dlambda, z) -> float:
+    """lyaf_angstrom_to_kms: velocity width of ``dlambda`` A at Lyman alpha at ``z``."""
+    return float(load().lyaf_angstrom_to_kms(float(dlambda), float(z)))
+
+
+def lya_lyb_path_kms(proximity_kms=3000.0) -> float:
+    """lyaf_lya_lyb_path_kms: Lya-Lyb path length minus the proximity zone, km/s."""
+    return float(load().lyaf_lya_lyb_path_kms(float(proximity_kms)))
+
+
+def make_instrument_params(fwhm_kms, bin_kms, v_start_kms=0.0, noise_sigma=0.0, window_k=6.0):
+    return InstrumentParams(float(fwhm_kms), float(bin_kms), float(v_start_kms),
+                            float(noise_sigma), float(window_k))
+
+
+def instrument(F, dv, offsets, out_offsets, F_obs, fwhm_kms, bin_kms, v_start_kms=0.0,
+               noise=None, noise_sigma=0.0, window_k=6.0, stream=None):
+    """lyaf_instrument: line-spread convolution, resampling and noise of each
+    skewer's flux ``F`` (float32 device [P]) into ``F_obs`` (float32 device
+    [P_out]); ``noise`` holds standard-normal draws [P_out] when
+    ``noise_sigma > 0``."""
+    off, oo = _host_offsets(offsets), _host_offsets(out_offsets)
+    ip = make_instrument_params(fwhm_kms, bin_kms, v_start_kms, noise_sigma, window_k)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    _check(load().lyaf_instrument(len(off) - 1, off.ctypes.data_as(pi64), _ptr(dv), _ptr(F),
+                                  ctypes.byref(ip), oo.ctypes.data_as(pi64), _ptr(noise),
+                                  _ptr(F_obs), _stream(stream)),
+           "lyaf_instrument")
+    return F_obs
+
+
+def instrument_backward(grad_obs, dv, offsets, out_offsets, grad_F, fwhm_kms, bin_kms,
+                        v_start_kms=0.0, window_k=6.0, stream=None):
+    """lyaf_instrument_backward: grad_F [P] <- J^T grad_obs [P_out]."""
+    off, oo = _host_offsets(offsets), _host_offsets(out_offsets)
+    ip = make_instrument_params(fwhm_kms, bin_kms, v_start_kms, 0.0, window_k)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    _check(load().lyaf_instrument_backward(len(off) - 1, off.ctypes.data_as(pi64), _ptr(dv),
+                                           ctypes.byref(ip), oo.ctypes.data_as(pi64),
+                                           _ptr(grad_obs), _ptr(grad_F), _stream(stream)),
+           "lyaf_instrument_backward")
+    return grad_F
 
 
 def status_read(stream=None) -> int:
@@ -299,17 +360,54 @@ def _autograd():
             return (gd, gv, gT.to(T0.dtype), gg.to(gamma.dtype), None, None, None, None,
                     None, None, None)
 
-    return TauFlux
+    class Instrument(torch.autograd.Function):
+        """F -> mock observation (line-spread convolution, resampling, noise).
+
+        forward : lyaf_instrument; backward: lyaf_instrument_backward."""
+
+        @staticmethod
+        def forward(ctx, F, dv, offsets, out_offsets, fwhm_kms, bin_kms, v_start_kms, noise,
+                    noise_sigma, window_k):
+            F, dv = F.contiguous(), dv.contiguous()
+            n_out = int(_host_offsets(out_offsets)[-1])
+            out = torch.empty(n_out, device=F.device, dtype=torch.float32)
+            instrument(F, dv, offsets, out_offsets, out, fwhm_kms, bin_kms, v_start_kms,
+                       None if noise is None else noise.contiguous(), noise_sigma, window_k)
+            ctx.save_for_backward(dv)
+            ctx.cfg = (F.numel(), offsets, out_offsets, fwhm_kms, bin_kms, v_start_kms, window_k)
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            (dv,) = ctx.saved_tensors
+            P, offsets, out_offsets, fwhm_kms, bin_kms, v_start_kms, window_k = ctx.cfg
+            gF = torch.empty(P, device=dv.device, dtype=torch.float32)
+            instrument_backward(g.contiguous().float(), dv, offsets, out_offsets, gF, fwhm_kms,
+                                bin_kms, v_start_kms, window_k)
+            return gF, None, None, None, None, None, None, None, None, None
+
+    return TauFlux, Instrument
 
 
 _TauFlux = None
+_Instrument = None
 
 
 def tau_flux(delta, vpec, T0, gamma, dv, offsets, target_F, tau_ref=1.0, delta_pivot=10.0,
              window_k=6.0, implicit_A=True):
     """Differentiable (tau', F, A) for torch tensors on the GPU."""
-    global _TauFlux
+    global _TauFlux, _Instrument
     if _TauFlux is None:
-        _TauFlux = _autograd()
+        _TauFlux, _Instrument = _autograd()
     return _TauFlux.apply(delta, vpec, T0, gamma, dv, offsets, target_F, tau_ref,
                           delta_pivot, window_k, implicit_A)
+
+
+def observe(F, dv, offsets, out_offsets, fwhm_kms, bin_kms, v_start_kms=0.0, noise=None,
+            noise_sigma=0.0, window_k=6.0):
+    """Differentiable mock observation of ``F`` (torch tensors on the GPU)."""
+    global _TauFlux, _Instrument
+    if _Instrument is None:
+        _TauFlux, _Instrument = _autograd()
+    return _Instrument.apply(F, dv, offsets, out_offsets, fwhm_kms, bin_kms, v_start_kms, noise,
+                             noise_sigma, window_k)

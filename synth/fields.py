@@ -200,6 +200,30 @@ def config5(seed: int = 5) -> Workload:
                             0.8, 6.0, seed)
 
 
+def gpc_lowres(seed: int = 6, n_skewers: int = 4096) -> Workload:
+    """Sight-lines through a 1 Gpc, 4096^3 box at z = 3 (Section 3.2): 4096 px
+    of ~244 comoving kpc, i.e. dv = 18.3 km/s at H(z=3) = 300.2 km/s/Mpc;
+    T0 = 1.7e4 K, gamma = 1.3 (Section 3), target <F> = 0.72 (Section 2.3),
+    C1 field statistics."""
+    return uniform_workload(f"Gpc {n_skewers}x4096", n_skewers, 4096, 18.3, 1.0, 1.7e4, 1.3,
+                            0.72, 6.0, seed)
+
+
+# Instrument settings as the paper prints them (widths in km/s or Angstrom;
+# Angstrom widths are converted at the model redshift by whoever uses them).
+REDSHIFT = 3.0
+INSTRUMENT_HIGH_RES = dict(fwhm_kms=7.0, bin_angstrom=0.05, snr=50.0)  # Section 3.1
+INSTRUMENT_BOSS = dict(fwhm_angstrom=3.63, bin_angstrom=1.0375, snr=5.0,
+                       proximity_kms=3000.0)  # Section 3.2
+INSTRUMENT_SDSS = dict(fwhm_kms=170.0, bin_angstrom=1.0, snr=3.8)  # Section 4.2
+
+
+def noise_draws(n: int, seed: int) -> np.ndarray:
+    """Standard-normal draws for the additive noise, float32 [n]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(n).astype(np.float32)
+
+
 def small_workload(n_skewers=8, n_pix=256, seed=11, sigma_lnD=1.0, dv=2.0,
                    T0=1.5e4, gamma=1.5, target_F=0.8, window_k=6.0):
     return uniform_workload(f"small {n_skewers}x{n_pix}", n_skewers, n_pix, dv,

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "lyaf.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(lyaf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|double|const char \*)\s*(lyaf_\w+)\s*\(", src, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -162,3 +162,46 @@ def test_peaks_library_exports_and_rejects_null():
     for n in names:
         assert hasattr(lib, n)
     assert lib.lyaf_peaks_measure(None, None) == -1
+
+
+def _ins(lib, off=(0, 10), oo=(0, 4), fwhm=7.0, bin_kms=3.0, v0=0.0, sigma=0.0, k=6.0,
+         ptrs=True, noise=False, S=None, backward=False):
+    off = np.asarray(off, np.int64)
+    oo = np.asarray(oo, np.int64)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    d = ctypes.c_void_p(0x1000) if ptrs else None  # never dereferenced: validation fails first
+    ip = L.InstrumentParams(fwhm, bin_kms, v0, sigma, k)
+    n = len(off) - 1 if S is None else S
+    if backward:
+        return lib.lyaf_instrument_backward(n, off.ctypes.data_as(pi64), d, ctypes.byref(ip),
+                                            oo.ctypes.data_as(pi64), d, d, None)
+    return lib.lyaf_instrument(n, off.ctypes.data_as(pi64), d, d, ctypes.byref(ip),
+                               oo.ctypes.data_as(pi64), ctypes.c_void_p(0x3000) if noise else None,
+                               d, None)
+
+
+@pytest.mark.parametrize("backward", [False, True])
+@pytest.mark.parametrize("kw", [
+    dict(fwhm=-1.0), dict(fwhm=float("nan")), dict(bin_kms=0.0), dict(bin_kms=float("inf")),
+    dict(v0=float("nan")), dict(sigma=-0.1), dict(k=-1.0), dict(S=-1),
+    dict(off=(1, 10)), dict(oo=(1, 4)), dict(off=(0, 10, 5), oo=(0, 4, 4)),
+    dict(off=(0, 10, 10), oo=(0, 4, 6)),  # bins for an empty skewer
+    dict(oo=(0, -1)), dict(ptrs=False),
+])
+def test_instrument_rejects_bad_arguments_on_host(lib, kw, backward):
+    assert _ins(lib, backward=backward, **kw) == L.LYAF_EINVAL
+
+
+def test_instrument_noise_and_empty_cases(lib):
+    # a noise scale needs the draws
+    assert _ins(lib, sigma=0.02) == L.LYAF_EINVAL
+    # nothing to do: no bins (forward) / no pixels (backward)
+    assert _ins(lib, oo=(0, 0)) == L.LYAF_OK
+    assert _ins(lib, off=(0,), oo=(0,), S=0, ptrs=False, backward=True) == L.LYAF_OK
+
+
+def test_instrument_unit_conversions_match_the_paper(lib):
+    # Section 3.2 prints the BOSS-like resolution as ~3.63 A and ~224 km/s at z = 3
+    assert abs(L.angstrom_to_kms(3.63, 3.0) - 224.0) < 0.5
+    assert L.angstrom_to_kms(1.0375, 3.0) == pytest.approx(63.9636, rel=1e-5)
+    assert 47000.0 < L.lya_lyb_path_kms(3000.0) < 49000.0
