@@ -92,6 +92,85 @@ def adjoint_section(L, torch, dev, fields, timed, reps, peak):
     return out
 
 
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (AMD-published)
+HBM_PEAK_GBS = 8000.0
+
+
+def instrument_case(L, torch, dev, fields, timed, reps, name, F, dvt, w, settings, path_kms):
+    """Time lyaf_instrument (and its backward) on the flux F of workload w."""
+    fwhm, bin_kms, sigma = settings
+    lens = np.diff(w.offsets)
+    n_out = []
+    covered = 0
+    for n, dv in zip(lens, w.dv):
+        L_kms = n * float(dv) if path_kms is None else min(n * float(dv), path_kms)
+        k = int(L_kms // bin_kms)
+        n_out.append(k)
+        covered += min(int(n), int(np.ceil(k * bin_kms / float(dv))) + 1)
+    oo = np.concatenate([[0], np.cumsum(n_out)]).astype(np.int64)
+    Po = int(oo[-1])
+    eps = torch.from_numpy(fields.noise_draws(Po, 31)).to(dev)
+    obs = torch.empty(Po, device=dev, dtype=torch.float32)
+    gF = torch.empty_like(F)
+    g = torch.from_numpy(fields.noise_draws(Po, 32)).to(dev)
+    run = lambda: L.instrument(F, dvt, w.offsets, oo, obs, fwhm, bin_kms, 0.0, eps, sigma, 6.0)
+    t_fwd = timed(run, reps)
+    t_bwd = timed(lambda: L.instrument_backward(g, dvt, w.offsets, oo, gF, fwhm, bin_kms, 0.0,
+                                                6.0), reps)
+    if L.status_read() != 0:
+        raise RuntimeError(f"device status set in the instrument case {name}")
+    # algorithmic work: taps within +-6 b_L per covered pixel (FMA = 2 flops);
+    # bytes: F read once, noise read and F_obs written per bin
+    bL = fwhm / (2.0 * np.sqrt(np.log(2.0)))
+    taps = 2 * int(np.floor(6.0 * bL / float(w.dv[0]))) + 1
+    flops = 2.0 * taps * covered
+    nbytes = 4.0 * covered + 8.0 * Po
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_fp64 = flops / (FP64_PEAK_TFLOPS * 1e12)
+    if t_fp64 >= t_hbm:
+        roof = {"bound": "fp64", "achieved": round(flops / t_fwd / 1e12, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(nbytes / t_fwd / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    return {"workload": name, "fwhm_kms": round(fwhm, 3), "bin_kms": round(bin_kms, 4),
+            "noise_sigma": sigma, "n_pix": int(w.n_pix), "covered_px": covered, "n_bins": Po,
+            "taps": taps, "forward_ms": round(t_fwd * 1e3, 4), "backward_ms": round(t_bwd * 1e3, 4),
+            "px_per_s": covered / t_fwd, "bins_per_s": Po / t_fwd,
+            "algorithmic_bytes": int(nbytes), "algorithmic_flops": flops,
+            "hbm_GBs": round(nbytes / t_fwd / 1e9, 1),
+            "fp64_TFLOPs": round(flops / t_fwd / 1e12, 3), "roofline": roof,
+            "kernel": "instrument_kernel"}
+
+
+def instrument_section(L, torch, dev, fields, timed, reps, F_c2, dvt_c2, w_c2):
+    """The instrument model (Sections 3.1, 3.2): the paper's high-resolution
+    setting on the 4096 x 4096 workload's flux, and its BOSS-like setting on the
+    Gpc box's flux (forward tau and mean-flux rescale first)."""
+    z = fields.REDSHIFT
+    hr, bo = fields.INSTRUMENT_HIGH_RES, fields.INSTRUMENT_BOSS
+    out = {}
+    print("bench: instrument high-res", file=sys.stderr, flush=True)
+    out["high_res"] = instrument_case(
+        L, torch, dev, fields, timed, reps, w_c2.name, F_c2, dvt_c2, w_c2,
+        (hr["fwhm_kms"], L.angstrom_to_kms(hr["bin_angstrom"], z), 1.0 / hr["snr"]), None)
+    w = fields.gpc_lowres()
+    print(f"bench: instrument BOSS-like on {w.name}", file=sys.stderr, flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = [t(x) for x in (w.delta, w.vpec, w.dv, w.T0, w.gamma)]
+    raw = torch.empty(w.n_pix, device=dev, dtype=torch.float32)
+    F = torch.empty_like(raw)
+    A = torch.empty((), device=dev, dtype=torch.float64)
+    L.tau(*d, w.offsets, raw, tau_ref=w.tau_ref, delta_pivot=w.delta_pivot, window_k=w.window_k)
+    L.normalise_mean_flux(raw, F, w.target_F, A)
+    out["boss"] = instrument_case(
+        L, torch, dev, fields, timed, reps, w.name, F, d[2], w,
+        (L.angstrom_to_kms(bo["fwhm_angstrom"], z), L.angstrom_to_kms(bo["bin_angstrom"], z),
+         1.0 / bo["snr"]), L.lya_lyb_path_kms(bo["proximity_kms"]))
+    return out
+
+
 def batched_section(L, torch, dev, fields, timed, reps):
     """The ragged 20,000-skewer batch (lengths 512-8192 px, dv 1-4 km/s, T0
     and gamma drawn per skewer): one tuned plan (persistent launch in a
@@ -195,6 +274,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
+    ap.add_argument("--no-instrument", action="store_true")
+    ap.add_argument("--instrument-only", action="store_true",
+                    help="only run the instrument section (forward and backward), for profiling")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint section (4096 x 2048), for profiling")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"])
@@ -230,7 +312,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_per_launch": 2 * src.numel() * 4}))
         return
-    if args.adjoint_only:
+    if args.adjoint_only or args.instrument_only:
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
         def timed(fn, n):
@@ -242,8 +324,20 @@ def main():
             ev1.synchronize()
             return ev0.elapsed_time(ev1) / n * 1e-3
 
-        print(json.dumps({"adjoint_only": True, **adjoint_section(
-            L, torch, dev, fields, timed, max(args.steps, 1), None)}), flush=True)
+        if args.adjoint_only:
+            print(json.dumps({"adjoint_only": True, **adjoint_section(
+                L, torch, dev, fields, timed, max(args.steps, 1), None)}), flush=True)
+            return
+        w = fields.config2()
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        d = [t(x) for x in (w.delta, w.vpec, w.dv, w.T0, w.gamma)]
+        raw = torch.empty(w.n_pix, device=dev, dtype=torch.float32)
+        F = torch.empty_like(raw)
+        A = torch.empty((), device=dev, dtype=torch.float64)
+        L.tau(*d, w.offsets, raw, window_k=w.window_k)
+        L.normalise_mean_flux(raw, F, w.target_F, A)
+        print(json.dumps({"instrument_only": True, **instrument_section(
+            L, torch, dev, fields, timed, max(args.steps, 1), F, d[2], w)}), flush=True)
         return
     peak = None
     if not args.no_peaks and not args.tau_only:
@@ -356,6 +450,9 @@ def main():
         extra["batched"] = batched_section(L, torch, dev, fields, timed, reps)
     if not args.no_adjoint:
         extra["adjoint"] = adjoint_section(L, torch, dev, fields, timed, reps, peak)
+    if not args.no_instrument:
+        plan.execute()  # F of this workload
+        extra["instrument"] = instrument_section(L, torch, dev, fields, timed, reps, F, dvt, w)
     if peak is not None:
         extra["peaks"] = {k: peak[k] for k in ("fma_lane_ops_per_s", "pair_per_s_exp",
                                                "pair_per_s_noexp", "c_exp_s", "c_valu_s",

@@ -278,6 +278,7 @@ InsArgs make_ins_args(Workspace *ws, const float *dv, const lyaf_instrument_para
   a.noise = nullptr;
   a.fwhm = ip->fwhm_kms;
   a.bin = ip->bin_kms;
+  a.inv_bin = 1.0 / ip->bin_kms;
   a.v_start = ip->v_start_kms;
   a.sigma = ip->noise_sigma;
   a.window_k = ip->window_k;

@@ -12,42 +12,54 @@
 //            pixel i = [(i - 1/2) dv, (i + 1/2) dv)
 //   Fobs_k = Fbin_k + sigma eps_k
 //
-// Kernel layout.  A work item is (skewer, c): the bins whose lower edge lies in
-// pixels [c W, (c+1) W) from the first bin's edge, W = kInsWindow.  Their pixel
-// span (at most W + dv_bin/dv + 2 <= kInsTile pixels) is convolved in one
-// workgroup: the flux with its halo of M pixels on each side is staged in LDS
+// Kernel layout.  The forward takes one skewer per workgroup and walks its
+// tiles: tile c holds the bins whose lower edge lies in pixels [c W, (c+1) W)
+// from the first bin's edge, W = kInsWindow.  Their pixel span (at most
+// W + dv_bin/dv + 2 <= kInsTile pixels) is convolved by the workgroup (the next
+// tile's reads are issued before this convolution starts): the flux with its halo of M pixels on each side is staged in LDS
 // as FP64 in 8 planes by index mod 8 (lane l reads element 8l + j from plane
-// j, so the reads of a wave are consecutive), each lane owns 8 consecutive
-// outputs and walks the taps 8 at a time with a sliding window of registers,
-// accumulating in FP64 (on gfx950 an FP64 FMA issues at the rate of an
-// unpacked FP32 one).  Taps come in blocks of kInsTapBlock, so any line-spread
-// width fits the same LDS.  The convolved span then becomes an FP64 prefix sum
-// in LDS, and each bin is the difference of that cumulative integral, linearly
-// interpolated, at its two edges, divided by its width.
+// j, so the reads of a wave are consecutive; the plane stride puts the 8
+// planes on different banks, so the staging writes do not collide either),
+// each lane owns 8 consecutive outputs and walks the taps 16 at a time with
+// two windows of registers used in turn, accumulating in FP64 (on gfx950 an
+// FP64 FMA issues at the rate of an unpacked FP32 one).  Taps come in blocks of
+// kInsTapBlock, so any line-spread width fits the same LDS.  The convolved span
+// then becomes an FP64 prefix sum in LDS, and each bin is the difference of
+// that cumulative integral, linearly interpolated, at its two edges, divided by
+// its width.
 //
 // The backward kernel is the transpose: each pixel gathers the gradients of
 // the bins it overlaps (times overlap / bin width), and the same convolution
 // runs over those values (the taps are even in m).
+#include <algorithm>
+
 #include "lyaf_internal.h"
 
 namespace lyaf {
 namespace {
 
 constexpr int kInsThreads = 256;
-constexpr int kInsPerLane = 8;                            // outputs per lane
-constexpr int kInsTile = kInsThreads * kInsPerLane;       // 2048 pixels
-constexpr int kInsWindow = 1792;                          // bin lower edges per item
-constexpr int kInsTapBlock = 256;                         // taps staged at once
-constexpr int kInsPlane = (kInsTile + kInsTapBlock) / 8;  // 288 doubles per plane
+constexpr int kInsPerLane = 8;                       // outputs per lane
+constexpr int kInsTile = kInsThreads * kInsPerLane;  // 2048 pixels
+constexpr int kInsWindow = 1792;                     // bin lower edges per item
+constexpr int kInsTapBlock = 256;                    // taps staged at once
+// Doubles per plane: at least (tile + tap block) / 8, and 2 * stride = 16 mod
+// 64 dwords, so that the 64 lanes of a staging write (8 planes x 8 rows) hit 64
+// different bank pairs.
+constexpr int kInsPlane = 296;
+static_assert(8 * kInsPlane >= kInsTile + kInsTapBlock + 16, "staged block must fit");
+static_assert((2 * kInsPlane) % 64 == 16, "planes must start on different banks");
 static_assert(kInsMaxRatio + kInsWindow + 4 <= kInsTile, "bin span must fit the tile");
-static_assert(kInsTapBlock % 8 == 0, "tap blocks are walked 8 at a time");
+static_assert(kInsTapBlock % 16 == 0, "tap blocks are walked 16 at a time");
 
 // Per-skewer geometry shared by both kernels.
 struct InsSkewer {
   int64_t off, n, out_off, n_out;
-  double dv;   // pixel width, km/s
-  double q;    // bin width in pixels
-  int M;       // taps m = -M .. M
+  double dv;       // pixel width, km/s
+  double inv_dv;   // 1 / dv
+  double q;        // bin width in pixels
+  double inv_q;    // 1 / q
+  int M;           // taps m = -M .. M
   bool half_ends;  // the two extreme taps are the same image (whole even box)
   bool ok;
 };
@@ -59,15 +71,16 @@ __device__ InsSkewer ins_skewer(const InsArgs &a, int64_t s) {
   k.out_off = a.out_offsets[s];
   k.n_out = a.out_offsets[s + 1] - k.out_off;
   k.dv = (double)a.dv[s];
-  k.q = a.bin / k.dv;
+  k.inv_dv = 1.0 / k.dv;
+  k.q = a.bin * k.inv_dv;
+  k.inv_q = k.dv * a.inv_bin;
   k.ok = k.dv > 0.0 && isfinite(k.dv) &&
          (k.n_out == 0 || (k.q <= (double)kInsMaxRatio &&
                            (double)k.n_out * a.bin <= (double)k.n * k.dv * (1.0 + 1e-9)));
   k.M = 0;
   k.half_ends = false;
   if (a.fwhm > 0.0) {
-    const double bL = a.fwhm * kInvTwoSqrtLn2;
-    const double reach = a.window_k * bL / k.dv;  // taps with |m dv| <= k b_L
+    const double reach = a.window_k * a.fwhm * kInvTwoSqrtLn2 * k.inv_dv;  // k b_L / dv
     if (a.window_k > 0.0 && reach < 0.5 * (double)(k.n - 1)) {
       k.M = (int)floor(reach);
     } else {  // the whole box, every offset at its minimal image
@@ -80,12 +93,15 @@ __device__ InsSkewer ins_skewer(const InsArgs &a, int64_t s) {
 
 // Lower edge of bin k in pixel coordinates (pixel i is [i, i+1)).
 __device__ inline double bin_edge(const InsArgs &a, const InsSkewer &k, int64_t bin) {
-  return (a.v_start + (double)bin * a.bin) / k.dv + 0.5;
+  return __builtin_fma((double)bin, a.bin, a.v_start) * k.inv_dv + 0.5;
 }
 
+// i mod n in [0, n) for |i| < 2^52, n >= 1.
 __device__ inline int64_t wrap_index(int64_t i, int64_t n) {
-  int64_t r = i % n;
-  return r < 0 ? r + n : r;
+  int64_t r = i - (int64_t)floor((double)i / (double)n) * n;
+  if (r < 0) r += n;
+  if (r >= n) r -= n;
+  return r;
 }
 
 // LDS of one workgroup.
@@ -94,6 +110,10 @@ struct InsShared {
   double h[kInsTapBlock];   // taps of the current block
   double red[kInsThreads / 64];
 };
+
+__device__ inline void stage_store(InsShared &sh, int x, double v) {
+  sh.s[(x & 7) * kInsPlane + (x >> 3)] = v;
+}
 
 // Sum over the workgroup, in a fixed order.
 __device__ double block_sum_d(double v, double *red) {
@@ -107,111 +127,226 @@ __device__ double block_sum_d(double v, double *red) {
   return t;
 }
 
-// Convolution of a tile: acc[q] = sum_{u < T} h_u src(base + 8l + q + u) for the
-// lane's outputs t = 8l + q < span, with h_u = g((M - u) dv) (unnormalised;
-// the sum of the taps is returned).  src(x) yields the value at staged offset
-// x (x = 0 .. span + T - 2).
-template <class Src>
+// Taps u0 .. u0 + tbp - 1 of the walk (h_u = g((M - u) dv), zero past the tb
+// real ones) into sh.h; returns this thread's share of their sum.
+__device__ double stage_taps(const InsArgs &a, const InsSkewer &k, int u0, int tb, int tbp,
+                             InsShared &sh) {
+  double z_part = 0.0;
+  const double scale = a.fwhm > 0.0 ? k.dv / (a.fwhm * kInvTwoSqrtLn2) : 0.0;  // dv / b_L
+  for (int u = threadIdx.x; u < tbp; u += kInsThreads) {
+    double g = 0.0;
+    if (u < tb) {
+      const int m = k.M - (u0 + u);
+      if (a.fwhm > 0.0) {
+        const double x = (double)m * scale;
+        g = exp(-x * x);
+        if (k.half_ends && (m == k.M || m == -k.M)) g *= 0.5;
+      } else {
+        g = 1.0;  // M = 0: the identity
+      }
+    }
+    sh.h[u] = g;
+    z_part += g;
+  }
+  return z_part;
+}
+
+// Eight taps u .. u+7 against the window lo (elements 8l + u .. 8l + u + 7) and
+// hi (the next 8).
+__device__ inline void conv_step(int u, const double (&lo)[8], const double (&hi)[8],
+                                 double (&acc)[kInsPerLane], const InsShared &sh) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double h = sh.h[u + i];
+#pragma unroll
+    for (int q = 0; q < kInsPerLane; ++q)
+      acc[q] = __builtin_fma(h, (q + i < 8) ? lo[q + i] : hi[q + i - 8], acc[q]);
+  }
+}
+
+// acc[q] += sum_{u < tbp} h_u s[8l + q + u] over the staged block (tbp a
+// multiple of 16): lane l owns outputs 8l .. 8l + 7; element 8l + 8b + j of the
+// staged block sits in plane j at row l + b.
+__device__ inline void conv_block(int tbp, double (&acc)[kInsPerLane], const InsShared &sh) {
+  const double *p = sh.s + threadIdx.x;
+  double wa[8], wb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) wa[j] = p[j * kInsPlane];
+  for (int u = 0; u < tbp; u += 16) {
+    const int b = u >> 3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wb[j] = p[j * kInsPlane + b + 1];
+    conv_step(u, wa, wb, acc, sh);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wa[j] = p[j * kInsPlane + b + 2];
+    conv_step(u + 8, wb, wa, acc, sh);
+  }
+}
+
+// Convolution of a tile: acc[q] = sum_{u < T} h_u src(8l + q + u) for the lane's
+// outputs t = 8l + q < span, taps in blocks of kInsTapBlock (unnormalised; the
+// sum of the taps is returned).  src(x) yields the value at staged offset x
+// (x = 0 .. span + T - 2).  With kBatchLoads, src is cheap and valid for any
+// x >= 0 (its reads stay in bounds), and each thread issues all its staging
+// reads before it stores any, so their latencies overlap.
+template <bool kBatchLoads, class Src>
 __device__ double convolve_tile(const InsArgs &a, const InsSkewer &k, int span, Src src,
                                 double (&acc)[kInsPerLane], InsShared &sh) {
   const int T = 2 * k.M + 1;
   const int tid = threadIdx.x;
   const bool wave_active = (tid & ~63) * kInsPerLane < span;
-  const double inv_bL = a.fwhm > 0.0 ? 1.0 / (a.fwhm * kInvTwoSqrtLn2) : 0.0;
   double z_part = 0.0;
 #pragma unroll
   for (int q = 0; q < kInsPerLane; ++q) acc[q] = 0.0;
   for (int u0 = 0; u0 < T; u0 += kInsTapBlock) {
     const int tb = min(kInsTapBlock, T - u0);  // real taps in this block
-    const int tbp = (tb + 7) & ~7;             // walked taps (zero-padded)
+    const int tbp = (tb + 15) & ~15;           // walked taps (zero-padded)
     __syncthreads();  // the previous block's readers are done
-    for (int u = tid; u < tbp; u += kInsThreads) {
-      double g = 0.0;
-      if (u < tb) {
-        const int m = k.M - (u0 + u);
-        if (a.fwhm > 0.0) {
-          const double x = (double)m * k.dv * inv_bL;
-          g = exp(-x * x);
-          if (k.half_ends && (m == k.M || m == -k.M)) g *= 0.5;
-        } else {
-          g = 1.0;  // M = 0: the identity
-        }
-      }
-      sh.h[u] = g;
-      z_part += g;
-    }
+    z_part += stage_taps(a, k, u0, tb, tbp, sh);
     const int need = span + tbp - 1;  // staged offsets read by outputs < span
     const int real = span + tb - 1;   // offsets carrying real taps
-    for (int x = tid; x < need; x += kInsThreads)
-      sh.s[(x & 7) * kInsPlane + (x >> 3)] = x < real ? src(u0 + x) : 0.0;
-    __syncthreads();
-    if (wave_active) {
-      const double *p = sh.s + tid;
-      double wl[8], wh[8];
+    if constexpr (kBatchLoads) {
+      constexpr int kIt = (kInsTile + kInsTapBlock + kInsThreads - 1) / kInsThreads;
+      using V = decltype(src(0));
+      V v[kIt];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) wl[j] = p[j * kInsPlane];
-      for (int u = 0; u < tbp; u += 8) {
-        const int b = (u >> 3) + 1;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) wh[j] = p[j * kInsPlane + b];
-        double hh[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) hh[i] = sh.h[u + i];
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-          for (int q = 0; q < kInsPerLane; ++q) {
-            const double w = (q + i < 8) ? wl[q + i] : wh[q + i - 8];
-            acc[q] = __builtin_fma(hh[i], w, acc[q]);
-          }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) wl[j] = wh[j];
+      for (int j = 0; j < kIt; ++j) {
+        const int x = tid + j * kInsThreads;
+        const V y = src(u0 + x);
+        v[j] = x < real ? y : V(0);
       }
+#pragma unroll
+      for (int j = 0; j < kIt; ++j) {
+        const int x = tid + j * kInsThreads;
+        if (x < need) stage_store(sh, x, (double)v[j]);
+      }
+    } else {
+      for (int x = tid; x < need; x += kInsThreads) stage_store(sh, x, x < real ? src(u0 + x) : 0.0);
     }
+    __syncthreads();
+    if (wave_active) conv_block(tbp, acc, sh);
   }
   return block_sum_d(z_part, sh.red);
 }
 
-__global__ __launch_bounds__(kInsThreads) void instrument_kernel(InsArgs a,
-                                                                 const int2 *__restrict__ items) {
-  __shared__ InsShared sh;
-  const int2 item = items[blockIdx.x];
-  const InsSkewer k = ins_skewer(a, item.x);
-  if (!k.ok) {
-    if (item.y == 0 && threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
-    return;
-  }
-  // bins of this item: lower edges in [c W, (c+1) W) pixels from the first edge
-  const auto first_bin = [&](int64_t c) -> int64_t {
-    if (c == 0) return 0;
-    if (c * kInsWindow >= k.n) return k.n_out;  // past the last item
-    const double kb = ceil((double)(c * kInsWindow) / k.q);
-    return kb >= (double)k.n_out ? k.n_out : (int64_t)kb;
-  };
-  const int64_t k_lo = first_bin(item.y), k_hi = first_bin(item.y + 1);
-  if (k_lo >= k_hi) return;
-  const double xa = bin_edge(a, k, k_lo), xb = bin_edge(a, k, k_hi);
-  const int64_t p0 = (int64_t)floor(xa);
-  const int span = (int)((int64_t)floor(xb) - p0 + 1);
-  if (span > kInsTile) {  // excluded by the bin-width limit; never expected
-    if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
-    return;
-  }
-  const float *F = a.in + k.off;
-  const int64_t n = k.n;
-  const int64_t base = wrap_index(p0 - k.M, n);
-  const auto src = [&](int x) -> double {
-    int64_t i = base + x;
-    if (i >= n) i -= n;
-    if (i >= n) i %= n;
-    return (double)F[i];
-  };
-  double acc[kInsPerLane];
-  const double Z = convolve_tile(a, k, span, src, acc, sh);
+// Geometry of tile c of a skewer: the bins whose lower edge lies in pixels
+// [c W, (c+1) W) from the first bin's edge, and the pixels they cover.
+struct InsTile {
+  int64_t k_lo, k_hi;  // bins k_lo .. k_hi - 1 (none if k_lo >= k_hi)
+  int64_t p0;          // first pixel of the span (absolute; may lie outside [0, n))
+  double e_lo;         // lower edge of bin k_lo relative to p0, pixels
+  double xb;           // lower edge of bin k_hi, pixels
+  uint32_t base;       // (p0 - M) mod n: pixel of staged offset 0
+  int span;            // pixels covered
+};
 
-  // prefix sums of the convolved span: sh.s[t] = sum_{t' < t} Fc[t']
+__device__ inline int64_t first_bin(const InsSkewer &k, int64_t c) {
+  if (c == 0) return 0;
+  if (c * kInsWindow >= k.n) return k.n_out;  // past the last tile
+  const double kb = ceil((double)(c * kInsWindow) * k.inv_q);
+  return kb >= (double)k.n_out ? k.n_out : (int64_t)kb;
+}
+
+// Tile c, given tile c - 1 (prev, for c > 0): the lower bin and edge of a tile
+// are the upper ones of the one before, and its base moves with p0.
+__device__ InsTile ins_tile(const InsArgs &a, const InsSkewer &k, int c, const InsTile *prev) {
+  InsTile t;
+  double xa;
+  if (prev) {
+    t.k_lo = prev->k_hi;
+    xa = prev->xb;
+  } else {
+    t.k_lo = 0;
+    xa = bin_edge(a, k, 0);
+  }
+  t.k_hi = first_bin(k, c + 1);
+  t.p0 = 0;
+  t.e_lo = 0.0;
+  t.xb = xa;
+  t.base = 0;
+  t.span = 0;
+  if (t.k_lo < t.k_hi) {
+    t.xb = bin_edge(a, k, t.k_hi);
+    t.p0 = (int64_t)floor(xa);
+    t.e_lo = xa - (double)t.p0;
+    t.span = (int)((int64_t)floor(t.xb) - t.p0 + 1);
+    const int64_t step = prev ? t.p0 - prev->p0 : 0;  // 0 <= step <= kInsTile
+    if (prev && step < k.n) {
+      int64_t b = (int64_t)prev->base + step;
+      if (b >= k.n) b -= k.n;
+      t.base = (uint32_t)b;
+    } else {
+      t.base = (uint32_t)wrap_index(t.p0 - k.M, k.n);
+    }
+  }
+  return t;
+}
+
+constexpr int kStageIt = (kInsTile + kInsTapBlock + kInsThreads - 1) / kInsThreads;  // 10
+constexpr int kNzPre = 6;  // noise draws per thread read ahead
+
+// Staged offset x of a tile holds pixel (p0 - M + x) mod n; n <= 2^24, so 32
+// bits do.
+__device__ inline float tile_flux(const float *F, uint32_t n32, uint32_t base, int x) {
+  uint32_t i = base + (uint32_t)x;
+  if (i >= n32) i -= n32;
+  if (i >= n32) i %= n32;
+  return F[i];
+}
+
+// Reads of a tile whose taps fit one block, into registers: thread t holds
+// staged offsets t + 256 j (zero past the real ones).
+__device__ inline void tile_loads(const float *F, uint32_t n32, const InsTile &t, int T,
+                                  float (&v)[kStageIt]) {
+  const int real = t.span + T - 1;
+  if (n32 >= (uint32_t)(kStageIt * kInsThreads)) {
+    // the staged offsets wrap around the box at most once
+    uint32_t i = t.base + threadIdx.x;
+    if (i >= n32) i -= n32;
+#pragma unroll
+    for (int j = 0; j < kStageIt; ++j) {
+      v[j] = (int)threadIdx.x + j * kInsThreads < real ? F[i] : 0.0f;
+      i += kInsThreads;
+      if (i >= n32) i -= n32;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kStageIt; ++j) {
+      const int x = (int)threadIdx.x + j * kInsThreads;
+      v[j] = x < real ? tile_flux(F, n32, t.base, x) : 0.0f;
+    }
+  }
+}
+
+// Thread t writes the bins j0 .. j0 + cnt - 1 of a tile (consecutive, so that
+// neighbouring bins share the cumulative value at their common edge).
+__device__ inline void bin_range(const InsTile &t, int &j0, int &cnt) {
+  const int nb = (int)(t.k_hi - t.k_lo);
+  const int cb = (nb + kInsThreads - 1) / kInsThreads;
+  j0 = min((int)threadIdx.x * cb, nb);
+  cnt = min(cb, nb - j0);
+}
+
+__device__ inline void noise_loads(const InsArgs &a, const InsSkewer &k, const InsTile &t,
+                                   float (&nz)[kNzPre]) {
+  int j0, cnt;
+  bin_range(t, j0, cnt);
+#pragma unroll
+  for (int r = 0; r < kNzPre; ++r)
+    nz[r] = (a.noise && r < cnt) ? a.noise[k.out_off + t.k_lo + j0 + r] : 0.0f;
+}
+
+// Prefix sums of a convolved tile, then its bins (with the noise draws nz read
+// ahead for the first kNzPre of this thread's bins): each bin is the
+// difference of the interpolated cumulative integral at its edges
+// e(j) = e_lo + j q (relative to p0), divided by its width.
+__device__ void finish_tile(const InsArgs &a, const InsSkewer &k, const InsTile &t,
+                            const double (&acc)[kInsPerLane], double Z,
+                            const float (&nz)[kNzPre], InsShared &sh) {
+  const int span = t.span;
+  // sh.s[i] = sum_{i' < i} Fc[i']; only outputs inside the span enter (lanes
+  // past it hold garbage)
   const double invZ = 1.0 / Z;
-  // only outputs inside the span enter the sums (lanes past it hold garbage)
   const int t0 = threadIdx.x * kInsPerLane;
   double run = 0.0, loc[kInsPerLane];
 #pragma unroll
@@ -219,7 +354,6 @@ __global__ __launch_bounds__(kInsThreads) void instrument_kernel(InsArgs a,
     if (t0 + q < span) run += acc[q] * invZ;
     loc[q] = run;
   }
-  // exclusive scan of the lane totals over the workgroup
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double incl = run;
   for (int d = 1; d < 64; d <<= 1) {
@@ -237,18 +371,115 @@ __global__ __launch_bounds__(kInsThreads) void instrument_kernel(InsArgs a,
     if (t0 + q < span) sh.s[t0 + q + 1] = excl + loc[q];
   __syncthreads();
 
-  // bins: difference of the interpolated cumulative integral at their edges
   const auto cum = [&](double e) -> double {
     const int i = min((int)e, span - 1);
     const double f = e - (double)i;
-    return sh.s[i] + f * (sh.s[i + 1] - sh.s[i]);
+    return __builtin_fma(f, sh.s[i + 1] - sh.s[i], sh.s[i]);
   };
-  for (int64_t kb = k_lo + threadIdx.x; kb < k_hi; kb += kInsThreads) {
-    const double e0 = bin_edge(a, k, kb) - (double)p0;
-    const double e1 = bin_edge(a, k, kb + 1) - (double)p0;
-    double v = (cum(e1) - cum(e0)) / (e1 - e0);
-    if (a.noise) v += a.sigma * (double)a.noise[k.out_off + kb];
-    a.out[k.out_off + kb] = (float)v;
+  int j0, cnt;
+  bin_range(t, j0, cnt);
+  if (cnt <= 0) return;
+  float *out = a.out + k.out_off + t.k_lo + j0;
+  const float *noise = a.noise ? a.noise + k.out_off + t.k_lo + j0 : nullptr;
+  double c0 = cum(__builtin_fma((double)j0, k.q, t.e_lo));
+#pragma unroll
+  for (int r = 0; r < kNzPre; ++r) {
+    if (r < cnt) {
+      const double c1 = cum(__builtin_fma((double)(j0 + r + 1), k.q, t.e_lo));
+      out[r] = (float)__builtin_fma(c1 - c0, k.inv_q, a.sigma * (double)nz[r]);
+      c0 = c1;
+    }
+  }
+  for (int r = kNzPre; r < cnt; ++r) {
+    const double c1 = cum(__builtin_fma((double)(j0 + r + 1), k.q, t.e_lo));
+    out[r] = (float)__builtin_fma(c1 - c0, k.inv_q, a.sigma * (double)(noise ? noise[r] : 0.0f));
+    c0 = c1;
+  }
+}
+
+// Forward, skewers whose taps fit one block (2M + 1 <= kInsTapBlock): one
+// workgroup per skewer, walking its tiles in order.  The skewer's constants,
+// taps and their sum are formed once; while a tile is convolved, the flux and
+// noise reads of the next tile are already in flight.
+__global__ __launch_bounds__(kInsThreads) void instrument_kernel(
+    InsArgs a, const int2 *__restrict__ items) {
+  __shared__ InsShared sh;
+  const InsSkewer k = ins_skewer(a, items[blockIdx.x].x);
+  if (!k.ok) {
+    if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
+    return;
+  }
+  const int T = 2 * k.M + 1;
+  if (T > kInsTapBlock) return;  // instrument_wide_kernel's skewer
+  const float *F = a.in + k.off;
+  const uint32_t n32 = (uint32_t)k.n;
+  const int tbp = (T + 15) & ~15;
+  const int n_tiles = (int)((k.n + kInsWindow - 1) / kInsWindow);
+
+  InsTile t = ins_tile(a, k, 0, nullptr);
+  float v[kStageIt], nz[kNzPre];
+  tile_loads(F, n32, t, T, v);
+  noise_loads(a, k, t, nz);
+  const double Z = block_sum_d(stage_taps(a, k, 0, T, tbp, sh), sh.red);
+
+  for (int c = 0; c < n_tiles && t.k_lo < t.k_hi; ++c) {
+    if (t.span > kInsTile) {  // excluded by the bin-width limit; never expected
+      if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
+      return;
+    }
+    const int need = t.span + tbp - 1;
+    __syncthreads();  // the previous tile's readers are done
+#pragma unroll
+    for (int j = 0; j < kStageIt; ++j) {
+      const int x = (int)threadIdx.x + j * kInsThreads;
+      if (x < need) stage_store(sh, x, (double)v[j]);
+    }
+    __syncthreads();
+    // the next tile's reads land while this one is convolved
+    const InsTile tn = ins_tile(a, k, c + 1, &t);
+    const bool more = c + 1 < n_tiles && tn.k_lo < tn.k_hi;
+    float nzn[kNzPre];
+    if (more) {
+      tile_loads(F, n32, tn, T, v);
+      noise_loads(a, k, tn, nzn);
+    }
+    double acc[kInsPerLane];
+#pragma unroll
+    for (int q = 0; q < kInsPerLane; ++q) acc[q] = 0.0;
+    if ((int)(threadIdx.x & ~63u) * kInsPerLane < t.span) conv_block(tbp, acc, sh);
+    finish_tile(a, k, t, acc, Z, nz, sh);
+    if (!more) break;
+    t = tn;
+#pragma unroll
+    for (int j = 0; j < kNzPre; ++j) nz[j] = nzn[j];
+  }
+}
+
+// Forward, skewers with wider line-spread functions (2M + 1 > kInsTapBlock):
+// the taps are staged block by block for every tile.
+__global__ __launch_bounds__(kInsThreads) void instrument_wide_kernel(
+    InsArgs a, const int2 *__restrict__ items) {
+  __shared__ InsShared sh;
+  const InsSkewer k = ins_skewer(a, items[blockIdx.x].x);
+  if (!k.ok || 2 * k.M + 1 <= kInsTapBlock) return;  // reported by instrument_kernel
+  const float *F = a.in + k.off;
+  const uint32_t n32 = (uint32_t)k.n;
+  const int n_tiles = (int)((k.n + kInsWindow - 1) / kInsWindow);
+  InsTile t = ins_tile(a, k, 0, nullptr);
+  for (int c = 0; c < n_tiles && t.k_lo < t.k_hi; ++c) {
+    if (t.span > kInsTile) {  // excluded by the bin-width limit; never expected
+      if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
+      return;
+    }
+    float nz[kNzPre];
+    noise_loads(a, k, t, nz);
+    const uint32_t base = t.base;
+    const auto src = [&](int x) -> float { return tile_flux(F, n32, base, x); };
+    double acc[kInsPerLane];
+    const double Z = convolve_tile<true>(a, k, t.span, src, acc, sh);
+    finish_tile(a, k, t, acc, Z, nz, sh);
+    const InsTile tn = ins_tile(a, k, c + 1, &t);
+    t = tn;
   }
 }
 
@@ -284,20 +515,20 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
     const double L_hi = floor((x_last - (double)i) / nd);
     for (double L = L_lo; L <= L_hi; L += 1.0) {
       const double y = (double)i + L * nd;
-      int64_t kb = (int64_t)floor((y - x_first) / k.q) - 1;
+      int64_t kb = (int64_t)floor((y - x_first) * k.inv_q) - 1;
       if (kb < 0) kb = 0;
       for (; kb < k.n_out; ++kb) {
         const double e0 = bin_edge(a, k, kb);
         if (e0 >= y + 1.0) break;
         const double e1 = bin_edge(a, k, kb + 1);
         const double ov = fmin(y + 1.0, e1) - fmax(y, e0);
-        if (ov > 0.0) v += ov * (double)g[kb] / (e1 - e0);
+        if (ov > 0.0) v += ov * (double)g[kb] * k.inv_q;
       }
     }
     return v;
   };
   double acc[kInsPerLane];
-  const double Z = convolve_tile(a, k, span, src, acc, sh);
+  const double Z = convolve_tile<false>(a, k, span, src, acc, sh);
   const double invZ = 1.0 / Z;
   const int t0 = threadIdx.x * kInsPerLane;
 #pragma unroll
@@ -310,8 +541,7 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
 int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward) {
   if (n <= 0) return 0;
   if (backward) return (int)((n + kInsTile - 1) / kInsTile);
-  if (n_out <= 0) return 0;
-  return (int)((n + kInsWindow - 1) / kInsWindow);
+  return n_out > 0 ? 1 : 0;  // the forward takes a whole skewer per workgroup
 }
 
 hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items, bool backward,
@@ -320,9 +550,12 @@ hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_item
   if (backward)
     hipLaunchKernelGGL(instrument_backward_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0,
                        st, a, items);
-  else
+  else {
     hipLaunchKernelGGL(instrument_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0, st, a,
                        items);
+    hipLaunchKernelGGL(instrument_wide_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0, st,
+                       a, items);
+  }
   return hipGetLastError();
 }
 

@@ -138,7 +138,7 @@ struct InsArgs {
   const float *in;             // forward: F [P]; backward: grad of the bins [P_out]
   float *out;                  // forward: bins [P_out]; backward: grad of F [P]
   const float *noise;          // forward: [P_out] or null
-  double fwhm, bin, v_start, sigma, window_k;
+  double fwhm, bin, inv_bin, v_start, sigma, window_k;
   uint32_t *status;
 };
 int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward);
