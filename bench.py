@@ -96,7 +96,26 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (AMD-published)
 HBM_PEAK_GBS = 8000.0
 
 
-def instrument_case(L, torch, dev, fields, timed, reps, name, F, dvt, w, settings, path_kms):
+def instrument_traffic(case):
+    """HBM bytes per instrument forward launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record, or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "instrument_traffic.json")))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in ("lyaf_instrument.hip", "lyaf_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1105_4747_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    ent = rec["per_case"].get(case)
+    return None if ent is None else ent["traffic_bytes_per_launch"]
+
+
+def instrument_case(L, torch, dev, fields, timed, reps, case, name, F, dvt, w, settings,
+                    path_kms):
     """Time lyaf_instrument (and its backward) on the flux F of workload w."""
     fwhm, bin_kms, sigma = settings
     lens = np.diff(w.offsets)
@@ -134,6 +153,8 @@ def instrument_case(L, torch, dev, fields, timed, reps, name, F, dvt, w, setting
         roof = {"bound": "hbm", "achieved": round(nbytes / t_fwd / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = instrument_traffic(case)
+    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE)"
     return {"workload": name, "fwhm_kms": round(fwhm, 3), "bin_kms": round(bin_kms, 4),
             "noise_sigma": sigma, "n_pix": int(w.n_pix), "covered_px": covered, "n_bins": Po,
             "taps": taps, "forward_ms": round(t_fwd * 1e3, 4), "backward_ms": round(t_bwd * 1e3, 4),
@@ -153,7 +174,7 @@ def instrument_section(L, torch, dev, fields, timed, reps, F_c2, dvt_c2, w_c2):
     out = {}
     print("bench: instrument high-res", file=sys.stderr, flush=True)
     out["high_res"] = instrument_case(
-        L, torch, dev, fields, timed, reps, w_c2.name, F_c2, dvt_c2, w_c2,
+        L, torch, dev, fields, timed, reps, "high_res", w_c2.name, F_c2, dvt_c2, w_c2,
         (hr["fwhm_kms"], L.angstrom_to_kms(hr["bin_angstrom"], z), 1.0 / hr["snr"]), None)
     w = fields.gpc_lowres()
     print(f"bench: instrument BOSS-like on {w.name}", file=sys.stderr, flush=True)
@@ -165,7 +186,7 @@ def instrument_section(L, torch, dev, fields, timed, reps, F_c2, dvt_c2, w_c2):
     L.tau(*d, w.offsets, raw, tau_ref=w.tau_ref, delta_pivot=w.delta_pivot, window_k=w.window_k)
     L.normalise_mean_flux(raw, F, w.target_F, A)
     out["boss"] = instrument_case(
-        L, torch, dev, fields, timed, reps, w.name, F, d[2], w,
+        L, torch, dev, fields, timed, reps, "boss", w.name, F, d[2], w,
         (L.angstrom_to_kms(bo["fwhm_angstrom"], z), L.angstrom_to_kms(bo["bin_angstrom"], z),
          1.0 / bo["snr"]), L.lya_lyb_path_kms(bo["proximity_kms"]))
     return out

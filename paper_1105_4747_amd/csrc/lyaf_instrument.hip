@@ -397,10 +397,11 @@ __device__ void finish_tile(const InsArgs &a, const InsSkewer &k, const InsTile 
   }
 }
 
-// Forward, skewers whose taps fit one block (2M + 1 <= kInsTapBlock): one
-// workgroup per skewer, walking its tiles in order.  The skewer's constants,
-// taps and their sum are formed once; while a tile is convolved, the flux and
-// noise reads of the next tile are already in flight.
+// Forward: one workgroup per skewer, walking its tiles in order.  When the
+// taps fit one block (2M + 1 <= kInsTapBlock) the skewer's taps and their sum
+// are formed once and, while a tile is convolved, the flux and noise reads of
+// the next tile are already in flight; wider line-spread functions stage the
+// taps block by block for every tile.
 __global__ __launch_bounds__(kInsThreads) void instrument_kernel(
     InsArgs a, const int2 *__restrict__ items) {
   __shared__ InsShared sh;
@@ -410,9 +411,29 @@ __global__ __launch_bounds__(kInsThreads) void instrument_kernel(
     return;
   }
   const int T = 2 * k.M + 1;
-  if (T > kInsTapBlock) return;  // instrument_wide_kernel's skewer
   const float *F = a.in + k.off;
   const uint32_t n32 = (uint32_t)k.n;
+  if (T > kInsTapBlock) {
+    // a wider line-spread function: taps staged block by block for every tile
+    const int nt = (int)((k.n + kInsWindow - 1) / kInsWindow);
+    InsTile t = ins_tile(a, k, 0, nullptr);
+    for (int c = 0; c < nt && t.k_lo < t.k_hi; ++c) {
+      if (t.span > kInsTile) {  // excluded by the bin-width limit; never expected
+        if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
+        return;
+      }
+      float nz[kNzPre];
+      noise_loads(a, k, t, nz);
+      const uint32_t base = t.base;
+      const auto src = [&](int x) -> double { return (double)tile_flux(F, n32, base, x); };
+      double acc[kInsPerLane];
+      const double Z = convolve_tile<false>(a, k, t.span, src, acc, sh);
+      finish_tile(a, k, t, acc, Z, nz, sh);
+      const InsTile tn = ins_tile(a, k, c + 1, &t);
+      t = tn;
+    }
+    return;
+  }
   const int tbp = (T + 15) & ~15;
   const int n_tiles = (int)((k.n + kInsWindow - 1) / kInsWindow);
 
@@ -452,34 +473,6 @@ __global__ __launch_bounds__(kInsThreads) void instrument_kernel(
     t = tn;
 #pragma unroll
     for (int j = 0; j < kNzPre; ++j) nz[j] = nzn[j];
-  }
-}
-
-// Forward, skewers with wider line-spread functions (2M + 1 > kInsTapBlock):
-// the taps are staged block by block for every tile.
-__global__ __launch_bounds__(kInsThreads) void instrument_wide_kernel(
-    InsArgs a, const int2 *__restrict__ items) {
-  __shared__ InsShared sh;
-  const InsSkewer k = ins_skewer(a, items[blockIdx.x].x);
-  if (!k.ok || 2 * k.M + 1 <= kInsTapBlock) return;  // reported by instrument_kernel
-  const float *F = a.in + k.off;
-  const uint32_t n32 = (uint32_t)k.n;
-  const int n_tiles = (int)((k.n + kInsWindow - 1) / kInsWindow);
-  InsTile t = ins_tile(a, k, 0, nullptr);
-  for (int c = 0; c < n_tiles && t.k_lo < t.k_hi; ++c) {
-    if (t.span > kInsTile) {  // excluded by the bin-width limit; never expected
-      if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
-      return;
-    }
-    float nz[kNzPre];
-    noise_loads(a, k, t, nz);
-    const uint32_t base = t.base;
-    const auto src = [&](int x) -> float { return tile_flux(F, n32, base, x); };
-    double acc[kInsPerLane];
-    const double Z = convolve_tile<true>(a, k, t.span, src, acc, sh);
-    finish_tile(a, k, t, acc, Z, nz, sh);
-    const InsTile tn = ins_tile(a, k, c + 1, &t);
-    t = tn;
   }
 }
 
@@ -553,8 +546,6 @@ hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_item
   else {
     hipLaunchKernelGGL(instrument_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0, st, a,
                        items);
-    hipLaunchKernelGGL(instrument_wide_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0, st,
-                       a, items);
   }
   return hipGetLastError();
 }
