@@ -216,6 +216,34 @@ double lyaf_angstrom_to_kms(double dlambda_angstrom, double z);
  * the proximity zone (Section 3.2: 3000 km/s). */
 double lyaf_lya_lyb_path_kms(double proximity_kms);
 
+/* ---- flux statistics (Section 4) ----
+ *
+ * Flux PDF (Section 4.2): 21 bins of width 0.05 centred on F = 0, 0.05, .., 1;
+ * bin j holds 0.05 j - 0.025 <= F < 0.05 j + 0.025, decided as
+ * j = floor((F + 0.025) * 20) in IEEE double on the exact float input.
+ *   F:      DEVICE [n_pix] float (any flux, e.g. F or the instrument's F_obs).
+ *   counts: DEVICE [24] int64, written: bins 0..20, then the number below the
+ *           first bin, at or above the end of the last, and NaN.  Exact.
+ * Errors: EINVAL for n_pix < 0 or NULL pointers (F may be NULL when n_pix = 0).
+ * The normalised PDF is counts[j] / (sum of counts[0..20] * 0.05). */
+int lyaf_flux_pdf(int64_t n_pix, const float *F, int64_t *counts, void *stream);
+
+/* 1D line-of-sight flux power spectrum (Section 4.3; the paper prints no
+ * estimator, the standard one is used): per skewer of N pixels of width dv,
+ * delta_j = F_j / mean_F - 1 and
+ *   P(k_m) = (dv / N) |sum_j delta_j exp(-2 pi i m j / N)|^2,
+ *   k_m = 2 pi m / (N dv) (s/km),  m = 0 .. N/2,
+ * computed in FP64 (an FFT per skewer) and stored as float.
+ *   offsets: HOST [S+1] int64; every N must be a power of two in [2, 8192].
+ *   dv:      DEVICE [S] float (> 0).
+ *   F:       DEVICE [P] float.
+ *   mean_F:  the mean flux that defines delta (> 0; e.g. the rescale target).
+ *   power:   DEVICE float, written: skewer s holds N_s/2 + 1 values from
+ *            sum_{s' < s} (N_s'/2 + 1).
+ * Errors: EINVAL (host); LYAF_STATUS_DOMAIN when dv <= 0 or not finite. */
+int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
+                    double mean_F, float *power, void *stream);
+
 /* ---- plans: the whole forward, tuned and captured once, replayed many times ----
  *
  * Section 2.3 applies the same steps to every spectrum of a survey: eq. (6) per

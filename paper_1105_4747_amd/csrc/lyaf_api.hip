@@ -268,6 +268,47 @@ int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int6
   return LYAF_OK;
 }
 
+// Host mirror of the power-spectrum offsets uploaded to a workspace.
+struct HostPsPlan {
+  std::vector<int64_t> offsets;  // [S+1]
+  int max_n = 0;
+  int64_t *h_off = nullptr, *h_mo = nullptr;
+  int64_t h_off_cap = 0, h_mo_cap = 0;
+};
+std::map<Workspace *, HostPsPlan> g_ps_plans;
+
+int ensure_ps_plan(Workspace *ws, int64_t S, const int64_t *offsets, HostPsPlan **out) {
+  HostPsPlan &hp = g_ps_plans[ws];
+  *out = &hp;
+  if ((int64_t)hp.offsets.size() == S + 1 &&
+      memcmp(hp.offsets.data(), offsets, sizeof(int64_t) * (size_t)(S + 1)) == 0)
+    return LYAF_OK;
+  hipError_t e;
+  if ((e = hipStreamSynchronize(ws->stream)) != hipSuccess) return map_err(e);
+  hp.offsets.clear();
+  if ((e = grow_host(hp.h_off, hp.h_off_cap, S + 1)) != hipSuccess ||
+      (e = grow_host(hp.h_mo, hp.h_mo_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(ws->ps_off, ws->ps_off_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(ws->ps_mo, ws->ps_mo_cap, S + 1)) != hipSuccess)
+    return map_err(e);
+  int max_n = 0;
+  hp.h_mo[0] = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t n = offsets[s + 1] - offsets[s];
+    hp.h_mo[s + 1] = hp.h_mo[s] + n / 2 + 1;
+    max_n = std::max(max_n, (int)n);
+  }
+  memcpy(hp.h_off, offsets, sizeof(int64_t) * (size_t)(S + 1));
+  if ((e = hipMemcpyAsync(ws->ps_off, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
+                          hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws->ps_mo, hp.h_mo, sizeof(int64_t) * (size_t)(S + 1),
+                          hipMemcpyHostToDevice, ws->stream)) != hipSuccess)
+    return map_err(e);
+  hp.max_n = max_n;
+  hp.offsets.assign(offsets, offsets + S + 1);
+  return LYAF_OK;
+}
+
 InsArgs make_ins_args(Workspace *ws, const float *dv, const lyaf_instrument_params *ip) {
   InsArgs a;
   a.offsets = ws->ins_off;
@@ -460,6 +501,38 @@ int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const fl
   a.in = grad_obs;
   a.out = grad_F;
   return map_err(launch_instrument(a, ws->ins_items, hp->n_items, true, st));
+}
+
+int lyaf_flux_pdf(int64_t n_pix, const float *F, int64_t *counts, void *stream) {
+  if (n_pix < 0 || !counts || (n_pix > 0 && !F)) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace *ws = nullptr;
+  int rc = get_ws(st, &ws);
+  if (rc) return rc;
+  hipError_t e = grow_dev(ws->pdf_part, ws->pdf_part_cap, (int64_t)kPdfMaxBlocks * kPdfCountSlots);
+  if (e != hipSuccess) return map_err(e);
+  return map_err(launch_flux_pdf(n_pix, F, ws->pdf_part, counts, st));
+}
+
+int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
+                    double mean_F, float *power, void *stream) {
+  if (n_skewers < 0 || !(mean_F > 0.0) || !isfinite(mean_F)) return LYAF_EINVAL;
+  if (n_skewers == 0) return LYAF_OK;
+  if (!offsets || !dv || !F || !power || offsets[0] != 0) return LYAF_EINVAL;
+  for (int64_t s = 0; s < n_skewers; ++s) {
+    const int64_t n = offsets[s + 1] - offsets[s];
+    if (n < 2 || n > kPsMaxN || (n & (n - 1)) != 0) return LYAF_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace *ws = nullptr;
+  int rc = get_ws(st, &ws);
+  if (rc) return rc;
+  HostPsPlan *hp = nullptr;
+  if ((rc = ensure_ps_plan(ws, n_skewers, offsets, &hp))) return rc;
+  return map_err(launch_flux_power(n_skewers, hp->max_n, F, ws->ps_off, ws->ps_mo, dv,
+                                   1.0 / mean_F, power, ws->status, st));
 }
 
 double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {

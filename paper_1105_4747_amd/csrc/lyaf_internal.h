@@ -79,6 +79,10 @@ struct Workspace {
   int64_t *ins_off = nullptr;  int64_t ins_off_cap = 0;
   int64_t *ins_oo = nullptr;   int64_t ins_oo_cap = 0;
   int2 *ins_items = nullptr;   int64_t ins_items_cap = 0;
+  // flux statistics: PDF partial counts, power-spectrum offsets (host mirror in the API)
+  uint32_t *pdf_part = nullptr; int64_t pdf_part_cap = 0;
+  int64_t *ps_off = nullptr;   int64_t ps_off_cap = 0;
+  int64_t *ps_mo = nullptr;    int64_t ps_mo_cap = 0;
 };
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
@@ -144,6 +148,15 @@ struct InsArgs {
 int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward);
 hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items, bool backward,
                              hipStream_t st);
+// Flux statistics (flux PDF, 1D flux power spectrum).
+constexpr int kPdfMaxBlocks = 1024;  // workgroups of the PDF counting kernel
+constexpr int kPdfCountSlots = 24;   // 21 bins, below, above, NaN
+constexpr int kPsMaxN = 8192;        // longest skewer of the power spectrum
+hipError_t launch_flux_pdf(int64_t n, const float *F, uint32_t *part, int64_t *counts,
+                           hipStream_t st);
+hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const int64_t *offsets,
+                             const int64_t *mode_off, const float *dv, double inv_mean, float *P,
+                             uint32_t *status, hipStream_t st);
 hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
                               const int64_t *item_base_dev, const float *g,
                               float *gdelta, float *gvpec, double *gT0,

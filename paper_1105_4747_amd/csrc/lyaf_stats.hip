@@ -1,0 +1,233 @@
+// lyaf_stats.hip -- flux statistics of Greig, Bolton & Wyithe (2011), Section 4:
+// the flux PDF (Section 4.2) and the 1D line-of-sight flux power spectrum
+// (Section 4.3).
+//
+// Flux PDF: 21 bins of width 0.05 centred on F = 0 .. 1; bin j holds
+// 0.05 j - 0.025 <= F < 0.05 j + 0.025, decided as j = floor((F + 0.025) * 20)
+// in FP64 on the exact FP32 input (one rounding after the sum, one after the
+// product).  Values below, at or above the end, and NaN are counted apart.
+// Each lane counts into its own LDS column (address slot * 256 + lane: every
+// lane on its own bank, no atomics), each workgroup writes its 24 counts, and a
+// second kernel sums them in a fixed order, so the output is exact and is
+// overwritten.
+//
+// Power spectrum: per skewer of N pixels (a power of two, 2 .. 8192),
+// delta_j = F_j / Fbar - 1 and P(k_m) = (dv / N) |sum_j delta_j e^{-2 pi i m j / N}|^2,
+// m = 0 .. N/2.  One workgroup per skewer packs the N reals into M = N/2
+// complex values z_j = delta_{2j} + i delta_{2j+1}, transforms them in LDS in
+// FP64 (Stockham passes of radix 4, then 2 when log2 M is odd, in place: each
+// thread holds its butterflies' outputs in registers across a barrier), with a
+// half-period twiddle table exp(-2 pi i t / M), t < M/2, in LDS, and unpacks
+// X_m = E_m + e^{-pi i m / M} O_m with E_m = (Z_m + conj Z_{M-m}) / 2 and
+// O_m = (Z_m - conj Z_{M-m}) / 2i.
+#include <algorithm>
+
+#include "lyaf_internal.h"
+
+namespace lyaf {
+namespace {
+
+constexpr int kPdfThreads = 256;
+constexpr int kPdfSlots = 24;  // 21 bins, below, above, NaN
+constexpr int kPsThreads = 256;
+
+__device__ inline int pdf_slot(float f) {
+  const double t = ((double)f + 0.025) * 20.0;
+  if (t != t) return 23;      // NaN
+  if (t < 0.0) return 21;     // below the first bin
+  if (t >= 21.0) return 22;   // at or above the end of the last bin
+  return (int)t;
+}
+
+__global__ __launch_bounds__(kPdfThreads) void flux_pdf_kernel(const float *__restrict__ F,
+                                                               int64_t n,
+                                                               uint32_t *__restrict__ part) {
+  __shared__ uint32_t cnt[kPdfSlots * kPdfThreads];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < kPdfSlots; ++b) cnt[b * kPdfThreads + tid] = 0;
+  const int64_t stride = (int64_t)gridDim.x * kPdfThreads;
+  int64_t i = (int64_t)blockIdx.x * kPdfThreads + tid;
+  // four values in flight per thread; the LDS adds return nothing, so they do
+  // not wait on one another (a lane's column is its own: no contention)
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const float f0 = F[i], f1 = F[i + stride], f2 = F[i + 2 * stride], f3 = F[i + 3 * stride];
+    atomicAdd(&cnt[pdf_slot(f0) * kPdfThreads + tid], 1u);
+    atomicAdd(&cnt[pdf_slot(f1) * kPdfThreads + tid], 1u);
+    atomicAdd(&cnt[pdf_slot(f2) * kPdfThreads + tid], 1u);
+    atomicAdd(&cnt[pdf_slot(f3) * kPdfThreads + tid], 1u);
+  }
+  for (; i < n; i += stride) atomicAdd(&cnt[pdf_slot(F[i]) * kPdfThreads + tid], 1u);
+  __syncthreads();
+  if (tid < kPdfSlots) {
+    uint32_t s = 0;  // rotated start: the 24 summing lanes read different banks
+    for (int l = 0; l < kPdfThreads; ++l) s += cnt[tid * kPdfThreads + ((l + tid) & 255)];
+    part[(int64_t)blockIdx.x * kPdfSlots + tid] = s;
+  }
+}
+
+__global__ void flux_pdf_sum_kernel(const uint32_t *__restrict__ part, int blocks,
+                                    int64_t *__restrict__ counts) {
+  const int b = threadIdx.x;
+  if (b >= kPdfSlots) return;
+  uint64_t s = 0;
+  for (int g = 0; g < blocks; ++g) s += part[(int64_t)g * kPdfSlots + b];
+  counts[b] = (int64_t)s;
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by -i and by +i
+__device__ inline double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }
+__device__ inline double2 mul_pi(double2 a) { return make_double2(-a.y, a.x); }
+
+// One in-place Stockham pass of radix R over M points with sub-transform size
+// Ns: butterfly j (k = j mod Ns) reads x_r = buf[j + r M/R], twiddles x_r by
+// w^r with w = e^{-2 pi i k / (R Ns)}, and writes its length-R DFT to
+// buf[(j - k) R + k + r Ns].
+template <int R>
+__device__ void stockham_pass(double2 *buf, const double2 *T, int M, int Ns) {
+  constexpr int B = (R == 4) ? 4 : 8;  // butterflies per thread at M = 4096
+  const int nb = M / R;
+  const int step = M / (R * Ns);  // twiddle-table stride
+  double2 y[B][R];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = (int)threadIdx.x + b * kPsThreads;
+    if (j < nb) {
+      const int k = j & (Ns - 1);
+      const double2 w = T[k * step];
+      double2 x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = buf[j + r * nb];
+      if constexpr (R == 4) {
+        const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+        const double2 a0 = x[0], a1 = cmul(x[1], w), a2 = cmul(x[2], w2), a3 = cmul(x[3], w3);
+        const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+        const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+        y[b][0] = cadd(s02, s13);
+        y[b][1] = cadd(d02, mul_mi(d13));
+        y[b][2] = csub(s02, s13);
+        y[b][3] = cadd(d02, mul_pi(d13));
+      } else {
+        const double2 a1 = cmul(x[1], w);
+        y[b][0] = cadd(x[0], a1);
+        y[b][1] = csub(x[0], a1);
+      }
+    }
+  }
+  __syncthreads();  // every read of this pass is done
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = (int)threadIdx.x + b * kPsThreads;
+    if (j < nb) {
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = y[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
+    const float *__restrict__ F, const int64_t *__restrict__ offsets,
+    const int64_t *__restrict__ mode_off, const float *__restrict__ dv, double inv_mean,
+    float *__restrict__ P, uint32_t *status) {
+  extern __shared__ double2 lds_ps[];
+  const int64_t s = blockIdx.x;
+  const int64_t off = offsets[s];
+  const int N = (int)(offsets[s + 1] - off);  // a power of two, 2 .. 8192 (host-checked)
+  const int M = N / 2;
+  const double dvs = (double)dv[s];
+  if (!(dvs > 0.0) || !isfinite(dvs)) {
+    if (threadIdx.x == 0) atomicOr(status, LYAF_STATUS_DOMAIN);
+    return;
+  }
+  double2 *buf = lds_ps;
+  double2 *T = lds_ps + M;
+  const int nt = max(M / 2, 1);
+  for (int t = threadIdx.x; t < nt; t += kPsThreads) {
+    double sn, cs;
+    sincospi(-2.0 * (double)t / (double)M, &sn, &cs);
+    T[t] = make_double2(cs, sn);
+  }
+  const float *f = F + off;
+  for (int j = threadIdx.x; j < M; j += kPsThreads)
+    buf[j] = make_double2(__builtin_fma((double)f[2 * j], inv_mean, -1.0),
+                          __builtin_fma((double)f[2 * j + 1], inv_mean, -1.0));
+  __syncthreads();
+  int Ns = 1;
+  while (Ns * 4 <= M) {
+    stockham_pass<4>(buf, T, M, Ns);
+    Ns *= 4;
+  }
+  if (Ns * 2 <= M) stockham_pass<2>(buf, T, M, Ns);
+
+  // unpack the real spectrum: X_m = E_m + e^{-pi i m / M} O_m, m = 0 .. M
+  double s1, c1;
+  sincospi(-1.0 / (double)M, &s1, &c1);
+  const double2 half_step = make_double2(c1, s1);
+  const double scale = dvs / (double)N;
+  float *out = P + mode_off[s];
+  for (int m = threadIdx.x; m <= M; m += kPsThreads) {
+    const double2 zm = buf[m == M ? 0 : m];
+    const double2 zr = buf[m == 0 ? 0 : M - m];
+    const double2 zc = make_double2(zr.x, -zr.y);
+    const double2 E = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
+    const double2 d = csub(zm, zc);
+    const double2 O = make_double2(0.5 * d.y, -0.5 * d.x);  // d / 2i
+    double2 tw;
+    if (m == M)
+      tw = make_double2(-1.0, 0.0);
+    else if ((m & 1) == 0)
+      tw = T[m >> 1];
+    else
+      tw = cmul(T[m >> 1], half_step);
+    const double2 X = cadd(E, cmul(tw, O));
+    out[m] = (float)(scale * __builtin_fma(X.x, X.x, X.y * X.y));
+  }
+}
+
+}  // namespace
+
+int pdf_blocks(int64_t n) {
+  const int64_t per_block = (int64_t)kPdfThreads * 16;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kPdfMaxBlocks, (n + per_block - 1) / per_block));
+}
+
+hipError_t launch_flux_pdf(int64_t n, const float *F, uint32_t *part, int64_t *counts,
+                           hipStream_t st) {
+  const int blocks = pdf_blocks(n);
+  hipLaunchKernelGGL(flux_pdf_kernel, dim3((unsigned)blocks), dim3(kPdfThreads), 0, st, F, n,
+                     part);
+  hipLaunchKernelGGL(flux_pdf_sum_kernel, dim3(1), dim3(32), 0, st, part, blocks, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const int64_t *offsets,
+                             const int64_t *mode_off, const float *dv, double inv_mean, float *P,
+                             uint32_t *status, hipStream_t st) {
+  if (n_skewers <= 0) return hipSuccess;
+  const int M = max_n / 2;
+  const size_t lds = sizeof(double2) * (size_t)(M + std::max(M / 2, 1));
+  static bool attr_set[64] = {false};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < 64 && !attr_set[dev]) {
+    e = hipFuncSetAttribute((const void *)flux_power_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double2) * (kPsMaxN / 2 + kPsMaxN / 4)));
+    if (e != hipSuccess) return e;
+    attr_set[dev] = true;
+  }
+  hipLaunchKernelGGL(flux_power_kernel, dim3((unsigned)n_skewers), dim3(kPsThreads), lds, st, F,
+                     offsets, mode_off, dv, inv_mean, P, status);
+  return hipGetLastError();
+}
+
+}  // namespace lyaf

@@ -41,7 +41,8 @@ EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_ba
             "lyaf_tau_backward", "lyaf_status_read", "lyaf_strerror", "lyaf_version",
             "lyaf_plan_create", "lyaf_plan_execute", "lyaf_plan_status", "lyaf_plan_describe",
             "lyaf_plan_destroy", "lyaf_instrument", "lyaf_instrument_backward",
-            "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms")
+            "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms", "lyaf_flux_pdf",
+            "lyaf_flux_power")
 
 
 class InstrumentParams(ctypes.Structure):
@@ -125,6 +126,10 @@ def load():
         lib.lyaf_angstrom_to_kms.restype = dbl
         lib.lyaf_lya_lyb_path_kms.argtypes = [dbl]
         lib.lyaf_lya_lyb_path_kms.restype = dbl
+        lib.lyaf_flux_pdf.argtypes = [i64, vp, vp, vp]
+        lib.lyaf_flux_pdf.restype = i32
+        lib.lyaf_flux_power.argtypes = [i64, pi64, vp, vp, dbl, vp, vp]
+        lib.lyaf_flux_power.restype = i32
         _lib = lib
         return lib
 
@@ -250,6 +255,34 @@ def instrument_backward(grad_obs, dv, offsets, out_offsets, grad_F, fwhm_kms, bi
                                            _ptr(grad_obs), _ptr(grad_F), _stream(stream)),
            "lyaf_instrument_backward")
     return grad_F
+
+
+PDF_SLOTS = 24  # lyaf_flux_pdf: 21 bins, below, above, NaN
+
+
+def flux_pdf(F, counts, stream=None):
+    """lyaf_flux_pdf: counts (int64 device [24]) of F (float32 device) in the 21
+    flux-PDF bins, then below, above and NaN."""
+    _check(load().lyaf_flux_pdf(F.numel(), _ptr(F), _ptr(counts), _stream(stream)),
+           "lyaf_flux_pdf")
+    return counts
+
+
+def mode_offsets(offsets):
+    """Offsets of lyaf_flux_power's output: skewer s holds N_s/2 + 1 modes."""
+    n = np.diff(_host_offsets(offsets))
+    return np.concatenate([[0], np.cumsum(n // 2 + 1)]).astype(np.int64)
+
+
+def flux_power(F, dv, offsets, mean_F, out, stream=None):
+    """lyaf_flux_power: per-skewer P(k_m), m = 0 .. N_s/2 (float32 device, laid
+    out by mode_offsets)."""
+    off = _host_offsets(offsets)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    _check(load().lyaf_flux_power(len(off) - 1, off.ctypes.data_as(pi64), _ptr(dv), _ptr(F),
+                                  float(mean_F), _ptr(out), _stream(stream)),
+           "lyaf_flux_power")
+    return out
 
 
 def status_read(stream=None) -> int:

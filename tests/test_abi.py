@@ -205,3 +205,35 @@ def test_instrument_unit_conversions_match_the_paper(lib):
     assert abs(L.angstrom_to_kms(3.63, 3.0) - 224.0) < 0.5
     assert L.angstrom_to_kms(1.0375, 3.0) == pytest.approx(63.9636, rel=1e-5)
     assert 47000.0 < L.lya_lyb_path_kms(3000.0) < 49000.0
+
+
+def test_flux_pdf_rejects_bad_arguments(lib):
+    p = ctypes.c_void_p(0x1000)
+    f = lib.lyaf_flux_pdf
+    assert f(-1, p, p, None) == L.LYAF_EINVAL
+    assert f(10, None, p, None) == L.LYAF_EINVAL
+    assert f(10, p, None, None) == L.LYAF_EINVAL
+
+
+@pytest.mark.parametrize("lens,mean_F", [
+    ([3], 0.8), ([1], 0.8), ([0], 0.8), ([16384], 0.8), ([4096, 100], 0.8),
+    ([64], 0.0), ([64], -1.0), ([64], float("nan")), ([64], float("inf")),
+])
+def test_flux_power_rejects_bad_arguments(lib, lens, mean_F):
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    p = ctypes.c_void_p(0x1000)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    assert lib.lyaf_flux_power(len(lens), off.ctypes.data_as(pi64), p, p, mean_F, p,
+                               None) == L.LYAF_EINVAL
+
+
+def test_flux_power_null_pointers_and_empty(lib):
+    off = np.array([0, 64], np.int64)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    p = ctypes.c_void_p(0x1000)
+    f = lib.lyaf_flux_power
+    assert f(1, off.ctypes.data_as(pi64), None, p, 0.8, p, None) == L.LYAF_EINVAL
+    assert f(1, off.ctypes.data_as(pi64), p, None, 0.8, p, None) == L.LYAF_EINVAL
+    assert f(1, off.ctypes.data_as(pi64), p, p, 0.8, None, None) == L.LYAF_EINVAL
+    assert f(1, None, p, p, 0.8, p, None) == L.LYAF_EINVAL
+    assert f(0, None, None, None, 0.8, None, None) == L.LYAF_OK
