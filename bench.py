@@ -192,6 +192,46 @@ def instrument_section(L, torch, dev, fields, timed, reps, F_c2, dvt_c2, w_c2):
     return out
 
 
+def stats_section(L, torch, dev, timed, reps, F, dvt, w):
+    """The flux statistics of Section 4 on the 4096 x 4096 workload's flux: the
+    21-bin flux PDF (lyaf_flux_pdf) and the per-skewer 1D flux power spectrum
+    (lyaf_flux_power), HIP events."""
+    P = int(F.numel())
+    counts = torch.empty(L.PDF_SLOTS, device=dev, dtype=torch.int64)
+    t_pdf = timed(lambda: L.flux_pdf(F, counts), reps)
+    mo = L.mode_offsets(w.offsets)
+    power = torch.empty(int(mo[-1]), device=dev, dtype=torch.float32)
+    t_ps = timed(lambda: L.flux_power(F, dvt, w.offsets, w.target_F, power), reps)
+    if L.status_read() != 0:
+        raise RuntimeError("device status set in the statistics section")
+    pdf_bytes = 4.0 * P
+    # power: 4 B per pixel in, 4 B per mode out; FP64 work of an N/2-point
+    # complex FFT per skewer (5 M log2 M flops) plus ~20 flops per mode
+    lens = np.diff(w.offsets)
+    ps_bytes = 4.0 * P + 4.0 * float(mo[-1])
+    ps_flops = float(sum(5.0 * (n // 2) * np.log2(max(n // 2, 1)) + 20.0 * (n // 2 + 1)
+                         for n in lens))
+    t_hbm, t_fp64 = ps_bytes / (HBM_PEAK_GBS * 1e9), ps_flops / (FP64_PEAK_TFLOPS * 1e12)
+    ps_roof = ({"bound": "hbm", "achieved": round(ps_bytes / t_ps / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"} if t_hbm >= t_fp64 else
+               {"bound": "fp64", "achieved": round(ps_flops / t_ps / 1e12, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"})
+    ps_roof["frac"] = round(ps_roof["achieved"] / ps_roof["peak"], 4)
+    pdf_gbs = pdf_bytes / t_pdf / 1e9
+    return {"workload": w.name, "n_pix": P,
+            "flux_pdf": {"ms": round(t_pdf * 1e3, 4), "px_per_s": P / t_pdf,
+                         "algorithmic_bytes": int(pdf_bytes),
+                         "roofline": {"bound": "hbm", "achieved": round(pdf_gbs, 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(pdf_gbs / HBM_PEAK_GBS, 4)},
+                         "kernel": "flux_pdf_kernel + flux_pdf_sum_kernel"},
+            "flux_power": {"ms": round(t_ps * 1e3, 4), "px_per_s": P / t_ps,
+                           "modes": int(mo[-1]), "algorithmic_bytes": int(ps_bytes),
+                           "algorithmic_fp64_flops": ps_flops,
+                           "fp64_TFLOPs": round(ps_flops / t_ps / 1e12, 3),
+                           "roofline": ps_roof, "kernel": "flux_power_kernel"}}
+
+
 def batched_section(L, torch, dev, fields, timed, reps):
     """The ragged 20,000-skewer batch (lengths 512-8192 px, dv 1-4 km/s, T0
     and gamma drawn per skewer): one tuned plan (persistent launch in a
@@ -296,6 +336,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--no-instrument", action="store_true")
+    ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--stats-only", action="store_true",
+                    help="only run the flux-statistics section (PDF, power spectrum), for profiling")
     ap.add_argument("--instrument-only", action="store_true",
                     help="only run the instrument section (forward and backward), for profiling")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -333,7 +376,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_per_launch": 2 * src.numel() * 4}))
         return
-    if args.adjoint_only or args.instrument_only:
+    if args.adjoint_only or args.instrument_only or args.stats_only:
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
         def timed(fn, n):
@@ -357,6 +400,10 @@ def main():
         A = torch.empty((), device=dev, dtype=torch.float64)
         L.tau(*d, w.offsets, raw, window_k=w.window_k)
         L.normalise_mean_flux(raw, F, w.target_F, A)
+        if args.stats_only:
+            print(json.dumps({"stats_only": True, **stats_section(
+                L, torch, dev, timed, max(args.steps, 1), F, d[2], w)}), flush=True)
+            return
         print(json.dumps({"instrument_only": True, **instrument_section(
             L, torch, dev, fields, timed, max(args.steps, 1), F, d[2], w)}), flush=True)
         return
@@ -474,6 +521,9 @@ def main():
     if not args.no_instrument:
         plan.execute()  # F of this workload
         extra["instrument"] = instrument_section(L, torch, dev, fields, timed, reps, F, dvt, w)
+    if not args.no_stats:
+        plan.execute()  # F of this workload
+        extra["flux_stats"] = stats_section(L, torch, dev, timed, reps, F, dvt, w)
     if peak is not None:
         extra["peaks"] = {k: peak[k] for k in ("fma_lane_ops_per_s", "pair_per_s_exp",
                                                "pair_per_s_noexp", "c_exp_s", "c_valu_s",

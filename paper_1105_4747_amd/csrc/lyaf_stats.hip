@@ -66,13 +66,17 @@ __global__ __launch_bounds__(kPdfThreads) void flux_pdf_kernel(const float *__re
   }
 }
 
-__global__ void flux_pdf_sum_kernel(const uint32_t *__restrict__ part, int blocks,
-                                    int64_t *__restrict__ counts) {
-  const int b = threadIdx.x;
-  if (b >= kPdfSlots) return;
+// Sum of the workgroups' counts (integers: exact in any order): one wave per
+// slot, each lane summing a strided share with its reads in flight, then a
+// shuffle reduction.
+__global__ __launch_bounds__(64) void flux_pdf_sum_kernel(const uint32_t *__restrict__ part,
+                                                          int blocks,
+                                                          int64_t *__restrict__ counts) {
+  const int slot = blockIdx.x;
   uint64_t s = 0;
-  for (int g = 0; g < blocks; ++g) s += part[(int64_t)g * kPdfSlots + b];
-  counts[b] = (int64_t)s;
+  for (int g = threadIdx.x; g < blocks; g += 64) s += part[(int64_t)g * kPdfSlots + slot];
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+  if (threadIdx.x == 0) counts[slot] = (int64_t)s;
 }
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -204,7 +208,7 @@ hipError_t launch_flux_pdf(int64_t n, const float *F, uint32_t *part, int64_t *c
   const int blocks = pdf_blocks(n);
   hipLaunchKernelGGL(flux_pdf_kernel, dim3((unsigned)blocks), dim3(kPdfThreads), 0, st, F, n,
                      part);
-  hipLaunchKernelGGL(flux_pdf_sum_kernel, dim3(1), dim3(32), 0, st, part, blocks, counts);
+  hipLaunchKernelGGL(flux_pdf_sum_kernel, dim3(kPdfSlots), dim3(64), 0, st, part, blocks, counts);
   return hipGetLastError();
 }
 
