@@ -218,6 +218,15 @@ INSTRUMENT_BOSS = dict(fwhm_angstrom=3.63, bin_angstrom=1.0375, snr=5.0,
 INSTRUMENT_SDSS = dict(fwhm_kms=170.0, bin_angstrom=1.0, snr=3.8)  # Section 4.2
 
 
+def synthetic_flux(lengths, seed: int, tau_mean: float = 0.35, sigma: float = 1.2) -> np.ndarray:
+    """A flux field F = exp(-tau) with a lognormal optical depth of the given
+    mean, drawn from the same Gaussian random field recipe as Delta (float32,
+    skewer-major).  It stands in for a forward flux where a stage downstream of
+    F is tested on its own."""
+    D, _ = lognormal_skewers(np.asarray(lengths, np.int64), sigma, seed)
+    return np.exp(-tau_mean * D.astype(np.float64)).astype(np.float32)
+
+
 def noise_draws(n: int, seed: int) -> np.ndarray:
     """Standard-normal draws for the additive noise, float32 [n]."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -85,3 +85,25 @@ def assert_grad_close(gpu, ref, what, rel=G_REL):
     err = np.abs(gpu - ref).max()
     assert err <= rel * scale, f"{what}: max err {err:.3g} vs scale {scale:.3g}"
     return err / scale if scale else 0.0
+
+
+def assert_mean_flux_root(tau, A, target_F, what="A", rel=A_REL):
+    """The mean-flux condition holds for the GPU's own outputs (a property that
+    holds at any size; no oracle): g(A) = <exp(-A tau)> - target_F must be zero
+    to within the A bar, |g| <= rel * A * |g'(A)|, g' = -<tau exp(-A tau)>."""
+    t = np.asarray(tau, np.float64)
+    e = np.exp(-A * t)
+    g = float(e.mean()) - target_F
+    dg = float((t * e).mean())
+    assert abs(g) <= rel * A * dg, f"{what}: g(A) = {g:.3g}, allowed {rel * A * dg:.3g}"
+    return abs(g) / (A * dg)
+
+
+def assert_subset_flux(raw_gpu_sub, ref_sub, target_F, what="subset F"):
+    """F parity on a subset normalised on its own on both sides: the GPU
+    rescales its own raw tau of the subset, the oracle its own (no value
+    crosses from one side to the other)."""
+    from oracle import oracle as O
+    _, F_gpu, _ = gpu_normalise(to_dev(np.ascontiguousarray(raw_gpu_sub, np.float32)), target_F)
+    _, F_ref, _ = O.normalise(np.asarray(ref_sub, np.float64), target_F)
+    return assert_F_close(F_gpu.cpu().numpy(), F_ref, what)

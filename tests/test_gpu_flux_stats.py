@@ -8,7 +8,7 @@ once to FP32, so |P_gpu - P_ref| <= 1e-6 P_ref + 1e-12 max_m P_ref per skewer.""
 import numpy as np
 import pytest
 
-from gpu_util import OnDevice, gpu_normalise, gpu_tau, to_dev
+from gpu_util import to_dev
 from oracle import flux_stats as FS
 from oracle import oracle as O
 from synth import fields
@@ -50,29 +50,28 @@ def assert_power_close(got, want, offsets, what):
 
 
 def c1_flux():
+    """The oracle's F of C1 (full sum, mean-flux rescale), as float32."""
     w = fields.config1()
-    _, F, _ = gpu_normalise(gpu_tau(w), w.target_F)
-    return w, F
+    raw = O.tau(w.delta, w.vpec, w.dv, w.T0, w.gamma, offsets=w.offsets, tau_ref=w.tau_ref,
+                delta_pivot=w.delta_pivot)
+    _, F, _ = O.normalise(raw, w.target_F)
+    return w, F.astype(np.float32)
 
 
 def test_pdf_of_the_c1_flux_and_its_noisy_observation():
-    import torch
-    from paper_1105_4747_amd import lyaf as L
     w, F = c1_flux()
     print("case: flux PDF of C1 F", flush=True)
-    got = gpu_pdf(F)
-    want = FS.flux_pdf(F.cpu().numpy())
-    assert np.array_equal(got, want), (got, want)
-    # BOSS-like noise (S/N 5) pushes values below 0 and above 1
+    assert np.array_equal(gpu_pdf(F), FS.flux_pdf(F))
+    # a BOSS-like noisy observation (S/N 5) of it, by the oracle: values below 0
+    # and above 1
     oo = np.arange(w.n_skewers + 1, dtype=np.int64) * 30
-    eps = to_dev(fields.noise_draws(int(oo[-1]), 3))
-    obs = torch.empty(int(oo[-1]), device="cuda:0", dtype=torch.float32)
-    L.instrument(F, to_dev(w.dv), w.offsets, oo, obs, 170.0, 61.65, 0.0, eps, 0.2, 6.0)
+    eps = fields.noise_draws(int(oo[-1]), 3).astype(np.float64)
+    obs = O.instrument(F.astype(np.float64), w.offsets, w.dv.astype(np.float64), oo, 170.0, 61.65,
+                       0.0, eps, 0.2).astype(np.float32)
     print("case: flux PDF of a noisy observation", flush=True)
-    got = gpu_pdf(obs)
-    want = FS.flux_pdf(obs.cpu().numpy())
+    want = FS.flux_pdf(obs)
     assert want[FS.PDF_BELOW] > 0 and want[FS.PDF_ABOVE] > 0
-    assert np.array_equal(got, want)
+    assert np.array_equal(gpu_pdf(obs), want)
 
 
 def test_pdf_at_bin_edges_and_special_values():
@@ -97,11 +96,10 @@ def test_pdf_of_nothing_and_of_one_value():
 
 
 @pytest.mark.slow
-def test_pdf_of_the_c2_flux():
-    w = fields.config2()
-    _, F, _ = gpu_normalise(gpu_tau(w), w.target_F)
-    print("case: flux PDF of C2 F (16.8M px)", flush=True)
-    assert np.array_equal(gpu_pdf(F), FS.flux_pdf(F.cpu().numpy()))
+def test_pdf_at_full_size():
+    F = fields.synthetic_flux(np.full(4096, 4096), 12)
+    print("case: flux PDF of a 4096 x 4096 synthetic flux (16.8M px)", flush=True)
+    assert np.array_equal(gpu_pdf(F), FS.flux_pdf(F))
 
 
 @pytest.mark.parametrize("lens", [[1024] * 8, [2, 4, 8, 16, 512, 4096, 8192, 2]])
@@ -120,8 +118,7 @@ def test_power_of_the_c1_flux():
     w, F = c1_flux()
     print("case: flux power of C1 F", flush=True)
     got = gpu_power(F, w.dv, w.offsets, w.target_F)
-    want, _ = FS.flux_power(F.cpu().numpy().astype(np.float64), w.offsets, w.dv.astype(np.float64),
-                            w.target_F)
+    want, _ = FS.flux_power(F.astype(np.float64), w.offsets, w.dv.astype(np.float64), w.target_F)
     assert_power_close(got, want, w.offsets, "C1")
 
 
@@ -141,13 +138,13 @@ def test_power_domain_status():
 @pytest.mark.parametrize("name", ["config2", "gpc_lowres"])
 def test_power_full_size_sampled(name):
     w = getattr(fields, name)()
-    d = OnDevice(w)
-    _, F, _ = gpu_normalise(gpu_tau(w, d=d), w.target_F)
-    print(f"case: flux power of {w.name}, 16 sampled skewers", flush=True)
-    got = gpu_power(F, w.dv, w.offsets, w.target_F)
-    Fh = F.cpu().numpy().astype(np.float64)
+    Fh = fields.synthetic_flux(np.diff(w.offsets), 13)
+    print(f"case: flux power of a synthetic flux of {w.name}'s shape, 16 sampled skewers",
+          flush=True)
+    got = gpu_power(Fh, w.dv, w.offsets, w.target_F)
     mo = FS.mode_offsets(w.offsets)
     for s in np.sort(np.random.default_rng(7).choice(w.n_skewers, 16, replace=False)):
         a, b = int(w.offsets[s]), int(w.offsets[s + 1])
-        want, _ = FS.flux_power(Fh[a:b], [0, b - a], float(w.dv[s]), w.target_F)
+        want, _ = FS.flux_power(Fh[a:b].astype(np.float64), [0, b - a], float(w.dv[s]),
+                                w.target_F)
         assert_power_close(got[mo[s]:mo[s + 1]], want, [0, b - a], f"{w.name} skewer {s}")

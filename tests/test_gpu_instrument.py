@@ -7,7 +7,7 @@ FP64 and rounds once to FP32, so about 6e-8 is expected), and for the adjoint
 import numpy as np
 import pytest
 
-from gpu_util import F_ABS, OnDevice, gpu_normalise, gpu_tau, to_dev
+from gpu_util import F_ABS, to_dev
 from oracle import oracle as O
 from synth import fields
 
@@ -151,27 +151,27 @@ def test_instrument_domain_status_and_other_skewers_unaffected():
 
 
 def _sampled(w, settings, path_kms, n_sample, seed):
-    """The workload's forward flux (tau, mean-flux rescale) on the GPU, then the
-    instrument on every skewer; sampled skewers against the oracle."""
+    """The instrument on every skewer of a workload's shape (a seeded synthetic
+    flux stands in for its forward flux); sampled skewers against the oracle."""
     import torch
     from paper_1105_4747_amd import lyaf as L
-    d = OnDevice(w)
-    _, F, _ = gpu_normalise(gpu_tau(w, d=d), w.target_F)
-    fwhm, bin_kms, sigma = settings
     lens = np.diff(w.offsets)
+    Fh = fields.synthetic_flux(lens, seed)
+    F = to_dev(Fh)
+    fwhm, bin_kms, sigma = settings
     oo = offs(n_bins(lens, w.dv, bin_kms, path_kms))
     eps = fields.noise_draws(int(oo[-1]), seed)
     out = torch.empty(int(oo[-1]), device="cuda:0", dtype=torch.float32)
-    L.instrument(F, d.dv, w.offsets, oo, out, fwhm, bin_kms, 0.0, to_dev(eps), sigma, 6.0)
+    L.instrument(F, to_dev(w.dv), w.offsets, oo, out, fwhm, bin_kms, 0.0, to_dev(eps), sigma, 6.0)
     torch.cuda.synchronize()
     assert L.status_read() == 0
     got = out.cpu().numpy().astype(np.float64)
-    Fh = F.cpu().numpy().astype(np.float64)
     pick = np.sort(np.random.default_rng(seed).choice(w.n_skewers, n_sample, replace=False))
     for s in pick:
         a, b = int(w.offsets[s]), int(w.offsets[s + 1])
-        ref = O.instrument(Fh[a:b], offs([b - a]), float(w.dv[s]), offs([oo[s + 1] - oo[s]]),
-                           fwhm, bin_kms, 0.0, eps[oo[s]:oo[s + 1]].astype(np.float64), sigma)
+        ref = O.instrument(Fh[a:b].astype(np.float64), offs([b - a]), float(w.dv[s]),
+                           offs([oo[s + 1] - oo[s]]), fwhm, bin_kms, 0.0,
+                           eps[oo[s]:oo[s + 1]].astype(np.float64), sigma)
         err = float(np.max(np.abs(got[oo[s]:oo[s + 1]] - ref)))
         assert err <= F_ABS, f"skewer {s}: max |dF_obs| {err:.3g}"
 

@@ -4,16 +4,18 @@ Every case runs the HIP library through its C ABI and compares element by
 element with the oracle on the same seeded inputs, at the tolerances stated in
 gpu_util.py.  Full-size workloads (4096 x 4096, 20,000 ragged skewers, the
 512 x 512 x 4096 box) run in the launch configuration the benchmark times and
-are compared on sampled skewers that the oracle computes in full, plus the
-mean-flux constant A against the oracle's root-find on the GPU's whole raw tau.
+are compared on sampled skewers that the oracle computes in full; the
+mean-flux constant is checked by the condition it solves on the GPU's own
+outputs (no oracle value), and F on a subset that each side normalises on its
+own.  No oracle input comes from the GPU.
 """
 import math
 
 import numpy as np
 import pytest
 
-from gpu_util import (OnDevice, assert_F_close, assert_tau_close, gpu_normalise, gpu_tau,
-                      A_REL)
+from gpu_util import (OnDevice, assert_F_close, assert_mean_flux_root, assert_subset_flux,
+                      assert_tau_close, gpu_normalise, gpu_tau, to_dev, A_REL)
 from oracle import oracle as O
 from synth import fields
 
@@ -108,11 +110,16 @@ def test_normalise_config1(c1):
     raw = gpu_tau(c1, d=d)
     ts, F, A = gpu_normalise(raw, c1.target_F)
     raw_np = raw.cpu().numpy().astype(np.float64)
-    # (i) root-find parity on the same raw tau
-    A_ref_same, _ = O.mean_flux_A(raw_np, c1.target_F)
-    assert abs(float(A.cpu()) / A_ref_same - 1) <= A_REL
+    # (i) root-find parity on the same input: the oracle's raw tau, rounded to
+    # float32, normalised by both sides
+    ref = oracle_tau(c1)
+    ref32 = ref.astype(np.float32)
+    _, _, A32 = gpu_normalise(to_dev(ref32), c1.target_F)
+    A_same, _ = O.mean_flux_A(ref32.astype(np.float64), c1.target_F)
+    assert abs(float(A32.cpu()) / A_same - 1) <= A_REL
+    assert_mean_flux_root(raw_np, float(A.cpu()), c1.target_F, "C1 A on its own tau")
     # (ii) end-to-end against the oracle's own tau
-    ts_ref, F_ref, A_ref = O.normalise(oracle_tau(c1), c1.target_F)
+    ts_ref, F_ref, A_ref = O.normalise(ref, c1.target_F)
     assert_tau_close(ts.cpu().numpy(), ts_ref, "C1 tau'")
     e = assert_F_close(F.cpu().numpy(), F_ref, "C1 F")
     assert abs(float(F.double().mean().cpu()) - c1.target_F) < 1e-6
@@ -226,13 +233,9 @@ def test_config2_full_size_sampled():
     ref = oracle_tau(sub)
     sel = np.concatenate([np.arange(w.offsets[s], w.offsets[s + 1]) for s in pick])
     worst = assert_tau_close(raw_np[sel], ref, "C2 sampled raw tau")
-    A_ref, _ = O.mean_flux_A(raw_np.astype(np.float64), w.target_F)
-    dA = abs(float(A.cpu()) / A_ref - 1)
-    assert dA <= A_REL
-    # F of the sampled skewers with the batch-wide A (oracle tau, oracle A on GPU tau)
-    F_ref = np.exp(-A_ref * ref)
-    eF = assert_F_close(F.cpu().numpy()[sel], F_ref, "C2 sampled F")
-    print(f"C2: worst tau err/tol {worst:.3f}, |dA/A| {dA:.2e}, max|dF| {eF:.2e}")
+    rA = assert_mean_flux_root(raw_np, float(A.cpu()), w.target_F, "C2 A")
+    eF = assert_subset_flux(raw_np[sel], ref, w.target_F, "C2 sampled F")
+    print(f"C2: worst tau err/tol {worst:.3f}, root residual {rA:.2e} of A, max|dF| {eF:.2e}")
 
 
 @pytest.mark.slow
@@ -251,9 +254,8 @@ def test_config3_ragged_full_size_sampled():
     ref = oracle_tau(sub)
     sel = np.concatenate([np.arange(w.offsets[s], w.offsets[s + 1]) for s in pick])
     worst = assert_tau_close(raw_np[sel], ref, "C3 sampled raw tau")
-    A_ref, _ = O.mean_flux_A(raw_np.astype(np.float64), w.target_F)
-    assert abs(float(A.cpu()) / A_ref - 1) <= A_REL
-    assert_F_close(F.cpu().numpy()[sel], np.exp(-A_ref * ref), "C3 sampled F")
+    assert_mean_flux_root(raw_np, float(A.cpu()), w.target_F, "C3 A")
+    assert_subset_flux(raw_np[sel], ref, w.target_F, "C3 sampled F")
     print(f"C3: worst tau err/tol {worst:.3f}")
 
 
@@ -280,7 +282,7 @@ def test_config4_box_sampled():
     # check the defining property instead: the mean flux is the target.
     Fm = float(F.double().mean().cpu())
     assert abs(Fm - w.target_F) <= 1e-6
-    eF = assert_F_close(F[sel_t].cpu().numpy(), np.exp(-float(A.cpu()) * ref), "C4 sampled F")
+    eF = assert_subset_flux(raw[sel_t].cpu().numpy(), ref, w.target_F, "C4 sampled F")
     print(f"C4: worst tau err/tol {worst:.3f}, <F>-target {Fm - w.target_F:.2e}, "
           f"max|dF| {eF:.2e}")
     del d, raw, ts, F, A
