@@ -531,8 +531,16 @@ int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, 
   if (rc) return rc;
   HostPsPlan *hp = nullptr;
   if ((rc = ensure_ps_plan(ws, n_skewers, offsets, &hp))) return rc;
+  if (!ws->ps_twiddle) {
+    hipError_t e = hipMalloc((void **)&ws->ps_twiddle, sizeof(double2) * (kPsMaxN / 4));
+    if (e != hipSuccess) {
+      ws->ps_twiddle = nullptr;
+      return map_err(e);
+    }
+    if ((e = launch_twiddles(ws->ps_twiddle, st)) != hipSuccess) return map_err(e);
+  }
   return map_err(launch_flux_power(n_skewers, hp->max_n, F, ws->ps_off, ws->ps_mo, dv,
-                                   1.0 / mean_F, power, ws->status, st));
+                                   1.0 / mean_F, ws->ps_twiddle, power, ws->status, st));
 }
 
 double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {

@@ -83,6 +83,7 @@ struct Workspace {
   uint32_t *pdf_part = nullptr; int64_t pdf_part_cap = 0;
   int64_t *ps_off = nullptr;   int64_t ps_off_cap = 0;
   int64_t *ps_mo = nullptr;    int64_t ps_mo_cap = 0;
+  double2 *ps_twiddle = nullptr;                      // [kPsMaxN / 4], built once
 };
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
@@ -154,9 +155,10 @@ constexpr int kPdfCountSlots = 24;   // 21 bins, below, above, NaN
 constexpr int kPsMaxN = 8192;        // longest skewer of the power spectrum
 hipError_t launch_flux_pdf(int64_t n, const float *F, uint32_t *part, int64_t *counts,
                            hipStream_t st);
+hipError_t launch_twiddles(double2 *T, hipStream_t st);  // kPsMaxN / 4 entries
 hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const int64_t *offsets,
-                             const int64_t *mode_off, const float *dv, double inv_mean, float *P,
-                             uint32_t *status, hipStream_t st);
+                             const int64_t *mode_off, const float *dv, double inv_mean,
+                             const double2 *T, float *P, uint32_t *status, hipStream_t st);
 hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
                               const int64_t *item_base_dev, const float *g,
                               float *gdelta, float *gvpec, double *gT0,

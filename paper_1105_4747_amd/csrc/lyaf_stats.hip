@@ -15,9 +15,10 @@
 // delta_j = F_j / Fbar - 1 and P(k_m) = (dv / N) |sum_j delta_j e^{-2 pi i m j / N}|^2,
 // m = 0 .. N/2.  One workgroup per skewer packs the N reals into M = N/2
 // complex values z_j = delta_{2j} + i delta_{2j+1}, transforms them in LDS in
-// FP64 (Stockham passes of radix 4, then 2 when log2 M is odd, in place: each
-// thread holds its butterflies' outputs in registers across a barrier), with a
-// half-period twiddle table exp(-2 pi i t / M), t < M/2, in LDS, and unpacks
+// FP64 (Stockham passes of radix 8, then one of radix 4 or 2 as log2 M needs,
+// in place: each thread holds its butterflies' outputs in registers across a
+// barrier), with a half-period twiddle table exp(-2 pi i t / M), t < M/2, in
+// LDS (copied from one table of the largest transform, built once), and unpacks
 // X_m = E_m + e^{-pi i m / M} O_m with E_m = (Z_m + conj Z_{M-m}) / 2 and
 // O_m = (Z_m - conj Z_{M-m}) / 2i.
 #include <algorithm>
@@ -88,13 +89,24 @@ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x -
 __device__ inline double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }
 __device__ inline double2 mul_pi(double2 a) { return make_double2(-a.y, a.x); }
 
+__device__ inline void dft4(double2 a0, double2 a1, double2 a2, double2 a3, double2 &y0,
+                            double2 &y1, double2 &y2, double2 &y3) {
+  const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+  y0 = cadd(s02, s13);
+  y1 = cadd(d02, mul_mi(d13));
+  y2 = csub(s02, s13);
+  y3 = cadd(d02, mul_pi(d13));
+}
+
 // One in-place Stockham pass of radix R over M points with sub-transform size
 // Ns: butterfly j (k = j mod Ns) reads x_r = buf[j + r M/R], twiddles x_r by
 // w^r with w = e^{-2 pi i k / (R Ns)}, and writes its length-R DFT to
-// buf[(j - k) R + k + r Ns].
+// buf[(j - k) R + k + r Ns].  A length-8 DFT is two length-4 DFTs of
+// x_k + x_{k+4} and (x_k - x_{k+4}) e^{-2 pi i k / 8}.
 template <int R>
 __device__ void stockham_pass(double2 *buf, const double2 *T, int M, int Ns) {
-  constexpr int B = (R == 4) ? 4 : 8;  // butterflies per thread at M = 4096
+  constexpr int B = 4096 / R / kPsThreads;  // butterflies per thread at M = 4096
   const int nb = M / R;
   const int step = M / (R * Ns);  // twiddle-table stride
   double2 y[B][R];
@@ -107,15 +119,30 @@ __device__ void stockham_pass(double2 *buf, const double2 *T, int M, int Ns) {
       double2 x[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = buf[j + r * nb];
-      if constexpr (R == 4) {
+      if constexpr (R == 8) {
+        const double2 w2 = cmul(w, w), w3 = cmul(w2, w), w4 = cmul(w2, w2);
+        const double2 w5 = cmul(w4, w), w6 = cmul(w3, w3), w7 = cmul(w6, w);
+        x[1] = cmul(x[1], w);
+        x[2] = cmul(x[2], w2);
+        x[3] = cmul(x[3], w3);
+        x[4] = cmul(x[4], w4);
+        x[5] = cmul(x[5], w5);
+        x[6] = cmul(x[6], w6);
+        x[7] = cmul(x[7], w7);
+        constexpr double h = 0.70710678118654752440;  // sqrt(1/2)
+        const double2 b0 = csub(x[0], x[4]);
+        const double2 t1 = csub(x[1], x[5]);
+        const double2 b1 = make_double2(h * (t1.x + t1.y), h * (t1.y - t1.x));  // * (1 - i)/sqrt2
+        const double2 b2 = mul_mi(csub(x[2], x[6]));
+        const double2 t3 = csub(x[3], x[7]);
+        const double2 b3 = make_double2(h * (t3.y - t3.x), -h * (t3.x + t3.y));  // * -(1 + i)/sqrt2
+        dft4(cadd(x[0], x[4]), cadd(x[1], x[5]), cadd(x[2], x[6]), cadd(x[3], x[7]), y[b][0],
+             y[b][2], y[b][4], y[b][6]);
+        dft4(b0, b1, b2, b3, y[b][1], y[b][3], y[b][5], y[b][7]);
+      } else if constexpr (R == 4) {
         const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
-        const double2 a0 = x[0], a1 = cmul(x[1], w), a2 = cmul(x[2], w2), a3 = cmul(x[3], w3);
-        const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
-        const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
-        y[b][0] = cadd(s02, s13);
-        y[b][1] = cadd(d02, mul_mi(d13));
-        y[b][2] = csub(s02, s13);
-        y[b][3] = cadd(d02, mul_pi(d13));
+        dft4(x[0], cmul(x[1], w), cmul(x[2], w2), cmul(x[3], w3), y[b][0], y[b][1], y[b][2],
+             y[b][3]);
       } else {
         const double2 a1 = cmul(x[1], w);
         y[b][0] = cadd(x[0], a1);
@@ -137,10 +164,22 @@ __device__ void stockham_pass(double2 *buf, const double2 *T, int M, int Ns) {
   __syncthreads();
 }
 
+// Twiddle table of the largest transform, exp(-2 pi i t / 4096), t < 2048; the
+// table of a transform of M points is every (4096 / M)-th entry.
+constexpr int kTwMax = kPsMaxN / 2;
+__global__ void twiddle_kernel(double2 *__restrict__ T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < kTwMax / 2) {
+    double sn, cs;
+    sincospi(-2.0 * (double)t / (double)kTwMax, &sn, &cs);
+    T[t] = make_double2(cs, sn);
+  }
+}
+
 __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
     const float *__restrict__ F, const int64_t *__restrict__ offsets,
     const int64_t *__restrict__ mode_off, const float *__restrict__ dv, double inv_mean,
-    float *__restrict__ P, uint32_t *status) {
+    const double2 *__restrict__ Tg, float *__restrict__ P, uint32_t *status) {
   extern __shared__ double2 lds_ps[];
   const int64_t s = blockIdx.x;
   const int64_t off = offsets[s];
@@ -154,18 +193,19 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
   double2 *buf = lds_ps;
   double2 *T = lds_ps + M;
   const int nt = max(M / 2, 1);
-  for (int t = threadIdx.x; t < nt; t += kPsThreads) {
-    double sn, cs;
-    sincospi(-2.0 * (double)t / (double)M, &sn, &cs);
-    T[t] = make_double2(cs, sn);
-  }
+  const int tstride = kTwMax / M;
+  for (int t = threadIdx.x; t < nt; t += kPsThreads) T[t] = Tg[t * tstride];
   const float *f = F + off;
   for (int j = threadIdx.x; j < M; j += kPsThreads)
     buf[j] = make_double2(__builtin_fma((double)f[2 * j], inv_mean, -1.0),
                           __builtin_fma((double)f[2 * j + 1], inv_mean, -1.0));
   __syncthreads();
   int Ns = 1;
-  while (Ns * 4 <= M) {
+  while (Ns * 8 <= M) {
+    stockham_pass<8>(buf, T, M, Ns);
+    Ns *= 8;
+  }
+  if (Ns * 4 <= M) {
     stockham_pass<4>(buf, T, M, Ns);
     Ns *= 4;
   }
@@ -212,9 +252,14 @@ hipError_t launch_flux_pdf(int64_t n, const float *F, uint32_t *part, int64_t *c
   return hipGetLastError();
 }
 
+hipError_t launch_twiddles(double2 *T, hipStream_t st) {
+  hipLaunchKernelGGL(twiddle_kernel, dim3((kTwMax / 2 + 255) / 256), dim3(256), 0, st, T);
+  return hipGetLastError();
+}
+
 hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const int64_t *offsets,
-                             const int64_t *mode_off, const float *dv, double inv_mean, float *P,
-                             uint32_t *status, hipStream_t st) {
+                             const int64_t *mode_off, const float *dv, double inv_mean,
+                             const double2 *T, float *P, uint32_t *status, hipStream_t st) {
   if (n_skewers <= 0) return hipSuccess;
   const int M = max_n / 2;
   const size_t lds = sizeof(double2) * (size_t)(M + std::max(M / 2, 1));
@@ -230,7 +275,7 @@ hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const
     attr_set[dev] = true;
   }
   hipLaunchKernelGGL(flux_power_kernel, dim3((unsigned)n_skewers), dim3(kPsThreads), lds, st, F,
-                     offsets, mode_off, dv, inv_mean, P, status);
+                     offsets, mode_off, dv, inv_mean, T, P, status);
   return hipGetLastError();
 }
 
