@@ -14,19 +14,22 @@
 //
 // Kernel layout.  The forward takes one skewer per workgroup and walks its
 // tiles: tile c holds the bins whose lower edge lies in pixels [c W, (c+1) W)
-// from the first bin's edge, W = kInsWindow.  Their pixel span (at most
-// W + dv_bin/dv + 2 <= kInsTile pixels) is convolved by the workgroup (the next
-// tile's reads are issued before this convolution starts): the flux with its halo of M pixels on each side is staged in LDS
-// as FP64 in 8 planes by index mod 8 (lane l reads element 8l + j from plane
-// j, so the reads of a wave are consecutive; the plane stride puts the 8
-// planes on different banks, so the staging writes do not collide either),
-// each lane owns 8 consecutive outputs and walks the taps 16 at a time with
-// two windows of registers used in turn, accumulating in FP64 (on gfx950 an
-// FP64 FMA issues at the rate of an unpacked FP32 one).  Taps come in blocks of
-// kInsTapBlock, so any line-spread width fits the same LDS.  The convolved span
-// then becomes an FP64 prefix sum in LDS, and each bin is the difference of
-// that cumulative integral, linearly interpolated, at its two edges, divided by
-// its width.
+// from the first bin's edge, W = kInsWindow, and their pixel span (at most
+// W + dv_bin/dv + 2 <= kInsTile pixels) is convolved by the workgroup.  The
+// flux of a tile with its halo of M pixels on each side sits in LDS in 8 planes
+// by index mod 8 (lane l reads element 8l + j from plane j, so the reads of a
+// wave are consecutive); each lane owns 8 consecutive outputs and walks the
+// taps 16 at a time with two windows of registers used in turn, accumulating
+// in FP64 (on gfx950 an FP64 FMA issues at the rate of an unpacked FP32 one).
+// When the taps fit one block of kInsTapBlock, the skewer's taps are formed
+// once and the flux is staged as FP32 in two buffers: the next tile is copied
+// from memory straight into the other buffer (global_load_lds, one wave
+// instruction per plane and 64 rows) while this one is convolved.  Wider
+// line-spread functions stage FP64 values and the taps block by block for every
+// tile (the plane stride puts those 8 planes on different banks).  The
+// convolved span then becomes an FP64 prefix sum in LDS, and each bin is the
+// difference of that cumulative integral, linearly interpolated, at its two
+// edges, divided by its width.
 //
 // The backward kernel is the transpose: each pixel gathers the gradients of
 // the bins it overlaps (times overlap / bin width), and the same convolution
@@ -130,7 +133,7 @@ __device__ double block_sum_d(double v, double *red) {
 // Taps u0 .. u0 + tbp - 1 of the walk (h_u = g((M - u) dv), zero past the tb
 // real ones) into sh.h; returns this thread's share of their sum.
 __device__ double stage_taps(const InsArgs &a, const InsSkewer &k, int u0, int tb, int tbp,
-                             InsShared &sh) {
+                             double *h) {
   double z_part = 0.0;
   const double scale = a.fwhm > 0.0 ? k.dv / (a.fwhm * kInvTwoSqrtLn2) : 0.0;  // dv / b_L
   for (int u = threadIdx.x; u < tbp; u += kInsThreads) {
@@ -145,7 +148,7 @@ __device__ double stage_taps(const InsArgs &a, const InsSkewer &k, int u0, int t
         g = 1.0;  // M = 0: the identity
       }
     }
-    sh.h[u] = g;
+    h[u] = g;
     z_part += g;
   }
   return z_part;
@@ -154,10 +157,10 @@ __device__ double stage_taps(const InsArgs &a, const InsSkewer &k, int u0, int t
 // Eight taps u .. u+7 against the window lo (elements 8l + u .. 8l + u + 7) and
 // hi (the next 8).
 __device__ inline void conv_step(int u, const double (&lo)[8], const double (&hi)[8],
-                                 double (&acc)[kInsPerLane], const InsShared &sh) {
+                                 double (&acc)[kInsPerLane], const double *taps) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const double h = sh.h[u + i];
+    const double h = taps[u + i];
 #pragma unroll
     for (int q = 0; q < kInsPerLane; ++q)
       acc[q] = __builtin_fma(h, (q + i < 8) ? lo[q + i] : hi[q + i - 8], acc[q]);
@@ -176,10 +179,10 @@ __device__ inline void conv_block(int tbp, double (&acc)[kInsPerLane], const Ins
     const int b = u >> 3;
 #pragma unroll
     for (int j = 0; j < 8; ++j) wb[j] = p[j * kInsPlane + b + 1];
-    conv_step(u, wa, wb, acc, sh);
+    conv_step(u, wa, wb, acc, sh.h);
 #pragma unroll
     for (int j = 0; j < 8; ++j) wa[j] = p[j * kInsPlane + b + 2];
-    conv_step(u + 8, wb, wa, acc, sh);
+    conv_step(u + 8, wb, wa, acc, sh.h);
   }
 }
 
@@ -202,7 +205,7 @@ __device__ double convolve_tile(const InsArgs &a, const InsSkewer &k, int span, 
     const int tb = min(kInsTapBlock, T - u0);  // real taps in this block
     const int tbp = (tb + 15) & ~15;           // walked taps (zero-padded)
     __syncthreads();  // the previous block's readers are done
-    z_part += stage_taps(a, k, u0, tb, tbp, sh);
+    z_part += stage_taps(a, k, u0, tb, tbp, sh.h);
     const int need = span + tbp - 1;  // staged offsets read by outputs < span
     const int real = span + tb - 1;   // offsets carrying real taps
     if constexpr (kBatchLoads) {
@@ -336,15 +339,66 @@ __device__ inline void noise_loads(const InsArgs &a, const InsSkewer &k, const I
     nz[r] = (a.noise && r < cnt) ? a.noise[k.out_off + t.k_lo + j0 + r] : 0.0f;
 }
 
+// LDS of the forward when the taps fit one block: two buffers of the raw flux
+// (FP32, 8 planes of kDmaRows rows: element x at plane x mod 8, row x / 8), the
+// prefix sums of the convolved tile, the taps.
+constexpr int kDmaRows = 320;  // 5 blocks of 64 rows
+static_assert(8 * kDmaRows >= kInsTile + kInsTapBlock + 16, "a staged tile must fit");
+struct InsDmaShared {
+  float f[2][8 * kDmaRows];
+  double pre[kInsTile + 8];
+  double h[kInsTapBlock];
+  double red[kInsThreads / 64];
+};
+
+// Staging of a tile straight from memory into LDS (global_load_lds: each lane's
+// dword lands at the wave's LDS base + 4 lane), one wave instruction per plane
+// and block of 64 rows, so no register holds it and the copy runs while the
+// workgroup computes.  Offsets past the real taps load a pixel of the tile
+// (they meet zero taps only).
+__device__ inline void tile_dma(const float *F, uint32_t n32, const InsTile &t, int T, int tbp,
+                                float *fbuf) {
+  const int need = t.span + tbp - 1;
+  const int real = t.span + T - 1;
+  const int nrb = (((need + 7) >> 3) + 63) >> 6;  // blocks of 64 rows, <= 5
+  const int lane = threadIdx.x & 63;
+  for (int q = threadIdx.x >> 6; q < 8 * nrb; q += kInsThreads / 64) {
+    const int j = q & 7, rb = q >> 3;
+    const int x = 8 * (rb * 64 + lane) + j;
+    uint32_t i = t.base + (uint32_t)(x < real ? x : 0);
+    if (i >= n32) i -= n32;
+    if (i >= n32) i %= n32;
+    __builtin_amdgcn_global_load_lds(F + i, fbuf + j * kDmaRows + rb * 64, 4, 0, 0);
+  }
+}
+
+// conv_block over a staged FP32 tile (each value converted once on load).
+__device__ inline void conv_block_f32(int tbp, double (&acc)[kInsPerLane], const float *fbuf,
+                                      const double *taps) {
+  const float *p = fbuf + threadIdx.x;
+  double wa[8], wb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) wa[j] = (double)p[j * kDmaRows];
+  for (int u = 0; u < tbp; u += 16) {
+    const int b = u >> 3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wb[j] = (double)p[j * kDmaRows + b + 1];
+    conv_step(u, wa, wb, acc, taps);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wa[j] = (double)p[j * kDmaRows + b + 2];
+    conv_step(u + 8, wb, wa, acc, taps);
+  }
+}
+
 // Prefix sums of a convolved tile, then its bins (with the noise draws nz read
 // ahead for the first kNzPre of this thread's bins): each bin is the
 // difference of the interpolated cumulative integral at its edges
 // e(j) = e_lo + j q (relative to p0), divided by its width.
 __device__ void finish_tile(const InsArgs &a, const InsSkewer &k, const InsTile &t,
                             const double (&acc)[kInsPerLane], double Z,
-                            const float (&nz)[kNzPre], InsShared &sh) {
+                            const float (&nz)[kNzPre], double *pre, double *red) {
   const int span = t.span;
-  // sh.s[i] = sum_{i' < i} Fc[i']; only outputs inside the span enter (lanes
+  // pre[i] = sum_{i' < i} Fc[i']; only outputs inside the span enter (lanes
   // past it hold garbage)
   const double invZ = 1.0 / Z;
   const int t0 = threadIdx.x * kInsPerLane;
@@ -361,20 +415,20 @@ __device__ void finish_tile(const InsArgs &a, const InsSkewer &k, const InsTile 
     if (lane >= d) incl += o;
   }
   __syncthreads();  // every wave is done with the staged values
-  if (lane == 63) sh.red[wv] = incl;
+  if (lane == 63) red[wv] = incl;
   __syncthreads();
   double excl = incl - run;
-  for (int w = 0; w < wv; ++w) excl += sh.red[w];
-  if (threadIdx.x == 0) sh.s[0] = 0.0;
+  for (int w = 0; w < wv; ++w) excl += red[w];
+  if (threadIdx.x == 0) pre[0] = 0.0;
 #pragma unroll
   for (int q = 0; q < kInsPerLane; ++q)
-    if (t0 + q < span) sh.s[t0 + q + 1] = excl + loc[q];
+    if (t0 + q < span) pre[t0 + q + 1] = excl + loc[q];
   __syncthreads();
 
   const auto cum = [&](double e) -> double {
     const int i = min((int)e, span - 1);
     const double f = e - (double)i;
-    return __builtin_fma(f, sh.s[i + 1] - sh.s[i], sh.s[i]);
+    return __builtin_fma(f, pre[i + 1] - pre[i], pre[i]);
   };
   int j0, cnt;
   bin_range(t, j0, cnt);
@@ -399,12 +453,17 @@ __device__ void finish_tile(const InsArgs &a, const InsSkewer &k, const InsTile 
 
 // Forward: one workgroup per skewer, walking its tiles in order.  When the
 // taps fit one block (2M + 1 <= kInsTapBlock) the skewer's taps and their sum
-// are formed once and, while a tile is convolved, the flux and noise reads of
-// the next tile are already in flight; wider line-spread functions stage the
-// taps block by block for every tile.
-__global__ __launch_bounds__(kInsThreads) void instrument_kernel(
+// are formed once and the next tile's flux is copied into the other LDS buffer
+// (and its noise draws read) while the current tile is convolved; wider
+// line-spread functions stage the taps block by block for every tile.
+union InsLds {
+  InsShared w;     // wide line-spread functions
+  InsDmaShared d;  // taps in one block
+};
+
+__global__ __launch_bounds__(kInsThreads) __attribute__((amdgpu_waves_per_eu(4))) void instrument_kernel(
     InsArgs a, const int2 *__restrict__ items) {
-  __shared__ InsShared sh;
+  __shared__ InsLds lds;
   const InsSkewer k = ins_skewer(a, items[blockIdx.x].x);
   if (!k.ok) {
     if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
@@ -415,6 +474,7 @@ __global__ __launch_bounds__(kInsThreads) void instrument_kernel(
   const uint32_t n32 = (uint32_t)k.n;
   if (T > kInsTapBlock) {
     // a wider line-spread function: taps staged block by block for every tile
+    InsShared &sh = lds.w;
     const int nt = (int)((k.n + kInsWindow - 1) / kInsWindow);
     InsTile t = ins_tile(a, k, 0, nullptr);
     for (int c = 0; c < nt && t.k_lo < t.k_hi; ++c) {
@@ -428,52 +488,52 @@ __global__ __launch_bounds__(kInsThreads) void instrument_kernel(
       const auto src = [&](int x) -> double { return (double)tile_flux(F, n32, base, x); };
       double acc[kInsPerLane];
       const double Z = convolve_tile<false>(a, k, t.span, src, acc, sh);
-      finish_tile(a, k, t, acc, Z, nz, sh);
+      finish_tile(a, k, t, acc, Z, nz, sh.s, sh.red);
       const InsTile tn = ins_tile(a, k, c + 1, &t);
       t = tn;
     }
     return;
   }
+  InsDmaShared &d = lds.d;
   const int tbp = (T + 15) & ~15;
   const int n_tiles = (int)((k.n + kInsWindow - 1) / kInsWindow);
 
   InsTile t = ins_tile(a, k, 0, nullptr);
-  float v[kStageIt], nz[kNzPre];
-  tile_loads(F, n32, t, T, v);
+  float nz[kNzPre];
+  if (t.k_lo < t.k_hi && t.span <= kInsTile) tile_dma(F, n32, t, T, tbp, d.f[0]);
   noise_loads(a, k, t, nz);
-  const double Z = block_sum_d(stage_taps(a, k, 0, T, tbp, sh), sh.red);
+  const double Z = block_sum_d(stage_taps(a, k, 0, T, tbp, d.h), d.red);
 
   for (int c = 0; c < n_tiles && t.k_lo < t.k_hi; ++c) {
     if (t.span > kInsTile) {  // excluded by the bin-width limit; never expected
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
       return;
     }
-    const int need = t.span + tbp - 1;
-    __syncthreads();  // the previous tile's readers are done
-#pragma unroll
-    for (int j = 0; j < kStageIt; ++j) {
-      const int x = (int)threadIdx.x + j * kInsThreads;
-      if (x < need) stage_store(sh, x, (double)v[j]);
-    }
+    // this tile's copy is complete for every wave
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    // the next tile's reads land while this one is convolved
+    // the next tile goes to the other buffer (last read by tile c - 1, whose
+    // readers are past the barriers of its prefix sums) while this one computes
     const InsTile tn = ins_tile(a, k, c + 1, &t);
-    const bool more = c + 1 < n_tiles && tn.k_lo < tn.k_hi;
+    const bool more = c + 1 < n_tiles && tn.k_lo < tn.k_hi && tn.span <= kInsTile;
     float nzn[kNzPre];
     if (more) {
-      tile_loads(F, n32, tn, T, v);
+      tile_dma(F, n32, tn, T, tbp, d.f[(c + 1) & 1]);
       noise_loads(a, k, tn, nzn);
     }
     double acc[kInsPerLane];
 #pragma unroll
     for (int q = 0; q < kInsPerLane; ++q) acc[q] = 0.0;
-    if ((int)(threadIdx.x & ~63u) * kInsPerLane < t.span) conv_block(tbp, acc, sh);
-    finish_tile(a, k, t, acc, Z, nz, sh);
-    if (!more) break;
+    if ((int)(threadIdx.x & ~63u) * kInsPerLane < t.span)
+      conv_block_f32(tbp, acc, d.f[c & 1], d.h);
+    finish_tile(a, k, t, acc, Z, nz, d.pre, d.red);
+    if (!(c + 1 < n_tiles && tn.k_lo < tn.k_hi)) break;
     t = tn;
 #pragma unroll
     for (int j = 0; j < kNzPre; ++j) nz[j] = nzn[j];
   }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
