@@ -17,8 +17,9 @@
 // complex values z_j = delta_{2j} + i delta_{2j+1}, transforms them in LDS in
 // FP64 (Stockham passes of radix 8, then one of radix 4 or 2 as log2 M needs,
 // in place: each thread holds its butterflies' outputs in registers across a
-// barrier), with a half-period twiddle table exp(-2 pi i t / M), t < M/2, in
-// LDS (copied from one table of the largest transform, built once), and unpacks
+// barrier), with twiddles read from one half-period table of the largest
+// transform, exp(-2 pi i t / 4096), t < 2048, built once (cached in L1/L2; the
+// table of M points is every (4096 / M)-th entry), and unpacks
 // X_m = E_m + e^{-pi i m / M} O_m with E_m = (Z_m + conj Z_{M-m}) / 2 and
 // O_m = (Z_m - conj Z_{M-m}) / 2i.
 #include <algorithm>
@@ -105,10 +106,10 @@ __device__ inline void dft4(double2 a0, double2 a1, double2 a2, double2 a3, doub
 // buf[(j - k) R + k + r Ns].  A length-8 DFT is two length-4 DFTs of
 // x_k + x_{k+4} and (x_k - x_{k+4}) e^{-2 pi i k / 8}.
 template <int R>
-__device__ void stockham_pass(double2 *buf, const double2 *T, int M, int Ns) {
+__device__ void stockham_pass(double2 *buf, const double2 *__restrict__ T, int M, int Ns) {
   constexpr int B = 4096 / R / kPsThreads;  // butterflies per thread at M = 4096
   const int nb = M / R;
-  const int step = M / (R * Ns);  // twiddle-table stride
+  const int step = (M / (R * Ns)) * (kPsMaxN / 2 / M);  // stride in the 4096-point table
   double2 y[B][R];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -191,10 +192,6 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
     return;
   }
   double2 *buf = lds_ps;
-  double2 *T = lds_ps + M;
-  const int nt = max(M / 2, 1);
-  const int tstride = kTwMax / M;
-  for (int t = threadIdx.x; t < nt; t += kPsThreads) T[t] = Tg[t * tstride];
   const float *f = F + off;
   for (int j = threadIdx.x; j < M; j += kPsThreads)
     buf[j] = make_double2(__builtin_fma((double)f[2 * j], inv_mean, -1.0),
@@ -202,14 +199,14 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
   __syncthreads();
   int Ns = 1;
   while (Ns * 8 <= M) {
-    stockham_pass<8>(buf, T, M, Ns);
+    stockham_pass<8>(buf, Tg, M, Ns);
     Ns *= 8;
   }
   if (Ns * 4 <= M) {
-    stockham_pass<4>(buf, T, M, Ns);
+    stockham_pass<4>(buf, Tg, M, Ns);
     Ns *= 4;
   }
-  if (Ns * 2 <= M) stockham_pass<2>(buf, T, M, Ns);
+  if (Ns * 2 <= M) stockham_pass<2>(buf, Tg, M, Ns);
 
   // unpack the real spectrum: X_m = E_m + e^{-pi i m / M} O_m, m = 0 .. M
   double s1, c1;
@@ -228,9 +225,9 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
     if (m == M)
       tw = make_double2(-1.0, 0.0);
     else if ((m & 1) == 0)
-      tw = T[m >> 1];
+      tw = Tg[(m >> 1) * (kTwMax / M)];
     else
-      tw = cmul(T[m >> 1], half_step);
+      tw = cmul(Tg[(m >> 1) * (kTwMax / M)], half_step);
     const double2 X = cadd(E, cmul(tw, O));
     out[m] = (float)(scale * __builtin_fma(X.x, X.x, X.y * X.y));
   }
@@ -262,7 +259,7 @@ hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const
                              const double2 *T, float *P, uint32_t *status, hipStream_t st) {
   if (n_skewers <= 0) return hipSuccess;
   const int M = max_n / 2;
-  const size_t lds = sizeof(double2) * (size_t)(M + std::max(M / 2, 1));
+  const size_t lds = sizeof(double2) * (size_t)M;
   static bool attr_set[64] = {false};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
