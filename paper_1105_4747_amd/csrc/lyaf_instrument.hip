@@ -55,6 +55,16 @@ static_assert((2 * kInsPlane) % 64 == 16, "planes must start on different banks"
 static_assert(kInsMaxRatio + kInsWindow + 4 <= kInsTile, "bin span must fit the tile");
 static_assert(kInsTapBlock % 16 == 0, "tap blocks are walked 16 at a time");
 
+// A double that every lane of the wave holds alike, moved to scalar registers:
+// FP64 arithmetic runs on the vector unit, so the skewer and tile constants
+// would otherwise take a register pair in every lane for the whole walk.
+__device__ inline double wave_uniform(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Per-skewer geometry shared by both kernels.
 struct InsSkewer {
   int64_t off, n, out_off, n_out;
@@ -73,18 +83,18 @@ __device__ InsSkewer ins_skewer(const InsArgs &a, int64_t s) {
   k.n = a.offsets[s + 1] - k.off;
   k.out_off = a.out_offsets[s];
   k.n_out = a.out_offsets[s + 1] - k.out_off;
-  k.dv = (double)a.dv[s];
-  k.inv_dv = 1.0 / k.dv;
-  k.q = a.bin * k.inv_dv;
-  k.inv_q = k.dv * a.inv_bin;
+  k.dv = wave_uniform((double)a.dv[s]);
+  k.inv_dv = wave_uniform(1.0 / k.dv);
+  k.q = wave_uniform(a.bin * k.inv_dv);
+  k.inv_q = wave_uniform(k.dv * a.inv_bin);
   k.ok = k.dv > 0.0 && isfinite(k.dv) &&
          (k.n_out == 0 || (k.q <= (double)kInsMaxRatio &&
-                           (double)k.n_out * a.bin <= (double)k.n * k.dv * (1.0 + 1e-9)));
+                           (double)k.n_out * a.bin <= (double)(int)k.n * k.dv * (1.0 + 1e-9)));
   k.M = 0;
   k.half_ends = false;
   if (a.fwhm > 0.0) {
     const double reach = a.window_k * a.fwhm * kInvTwoSqrtLn2 * k.inv_dv;  // k b_L / dv
-    if (a.window_k > 0.0 && reach < 0.5 * (double)(k.n - 1)) {
+    if (a.window_k > 0.0 && reach < 0.5 * (double)((int)k.n - 1)) {
       k.M = (int)floor(reach);
     } else {  // the whole box, every offset at its minimal image
       k.M = (int)(k.n / 2);
@@ -99,8 +109,8 @@ __device__ inline double bin_edge(const InsArgs &a, const InsSkewer &k, int64_t 
   return __builtin_fma((double)bin, a.bin, a.v_start) * k.inv_dv + 0.5;
 }
 
-// i mod n in [0, n) for |i| < 2^52, n >= 1.
-__device__ inline int64_t wrap_index(int64_t i, int64_t n) {
+// i mod n in [0, n) for |i| < 2^52, 1 <= n <= 2^24 (a skewer's length).
+__device__ inline int64_t wrap_index(int64_t i, int n) {
   int64_t r = i - (int64_t)floor((double)i / (double)n) * n;
   if (r < 0) r += n;
   if (r >= n) r -= n;
@@ -246,8 +256,9 @@ struct InsTile {
 __device__ inline int64_t first_bin(const InsSkewer &k, int64_t c) {
   if (c == 0) return 0;
   if (c * kInsWindow >= k.n) return k.n_out;  // past the last tile
-  const double kb = ceil((double)(c * kInsWindow) * k.inv_q);
-  return kb >= (double)k.n_out ? k.n_out : (int64_t)kb;
+  // c kInsWindow < n, so kb <= n / q + 1, about n_out + 1: exact as int64
+  const int64_t kb = (int64_t)ceil((double)(c * kInsWindow) * k.inv_q);
+  return kb >= k.n_out ? k.n_out : kb;
 }
 
 // Tile c, given tile c - 1 (prev, for c > 0): the lower bin and edge of a tile
@@ -269,9 +280,9 @@ __device__ InsTile ins_tile(const InsArgs &a, const InsSkewer &k, int c, const I
   t.base = 0;
   t.span = 0;
   if (t.k_lo < t.k_hi) {
-    t.xb = bin_edge(a, k, t.k_hi);
+    t.xb = wave_uniform(bin_edge(a, k, t.k_hi));
     t.p0 = (int64_t)floor(xa);
-    t.e_lo = xa - (double)t.p0;
+    t.e_lo = wave_uniform(xa - (double)t.p0);
     t.span = (int)((int64_t)floor(t.xb) - t.p0 + 1);
     const int64_t step = prev ? t.p0 - prev->p0 : 0;  // 0 <= step <= kInsTile
     if (prev && step < k.n) {
@@ -279,14 +290,14 @@ __device__ InsTile ins_tile(const InsArgs &a, const InsSkewer &k, int c, const I
       if (b >= k.n) b -= k.n;
       t.base = (uint32_t)b;
     } else {
-      t.base = (uint32_t)wrap_index(t.p0 - k.M, k.n);
+      t.base = (uint32_t)wrap_index(t.p0 - k.M, (int)k.n);
     }
   }
   return t;
 }
 
 constexpr int kStageIt = (kInsTile + kInsTapBlock + kInsThreads - 1) / kInsThreads;  // 10
-constexpr int kNzPre = 6;  // noise draws per thread read ahead
+constexpr int kNzPre = 4;  // noise draws per thread read ahead
 
 // Staged offset x of a tile holds pixel (p0 - M + x) mod n; n <= 2^24, so 32
 // bits do.
@@ -536,9 +547,95 @@ __global__ __launch_bounds__(kInsThreads) __attribute__((amdgpu_waves_per_eu(4))
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Adjoint of the binning for the cnt (<= 8) consecutive pixels i0 .. i0 + cnt
+// - 1 of one image range: the gradient reaching each from the bins over it,
+// overlap times the bin's gradient over the bin width, summed over the
+// pixel's images that meet [x_first, x_last).  A merge walk: the current bin,
+// its edges and its gradient carry from pixel to pixel, so each is formed
+// once per run.  out(p, h) receives pixel i0 + p.
+struct InsBinGeom {
+  double x_first, x_last;  // lower edges of bin 0 and of bin n_out, pixels
+  double nd, inv_nd;       // n and 1 / n
+};
+template <class GLoad, class Out>
+__device__ inline void bin_adjoint_run(const InsArgs &a, const InsSkewer &k, const InsBinGeom &G,
+                                       int64_t i0, int cnt, GLoad gload, Out out) {
+  double acc[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) acc[p] = 0.0;
+  // images y = i + L n of the run's pixels that meet the bins (a quotient
+  // rounded across an integer only drops or adds an image whose overlap is
+  // below 1e-9 px, or zero)
+  const double L_lo = ceil((G.x_first - (double)(i0 + cnt - 1) - 1.0) * G.inv_nd);
+  const double L_hi = floor((G.x_last - (double)i0) * G.inv_nd);
+  for (double L = L_lo; L <= L_hi; L += 1.0) {
+    const double y0 = (double)i0 + L * G.nd;
+    int64_t kb = (int64_t)floor((y0 - G.x_first) * k.inv_q) - 1;
+    if (kb < 0) kb = 0;
+    if (kb >= k.n_out) continue;
+    double e0 = bin_edge(a, k, kb), e1 = bin_edge(a, k, kb + 1);
+    while (e1 <= y0 && kb + 1 < k.n_out) {  // to the first bin that ends past y0
+      ++kb;
+      e0 = e1;
+      e1 = bin_edge(a, k, kb + 1);
+    }
+    double gk = (double)gload(kb) * k.inv_q;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (p < cnt) {
+        const double y = y0 + (double)p;
+        while (kb < k.n_out && e0 < y + 1.0) {
+          const double ov = fmin(y + 1.0, e1) - fmax(y, e0);
+          if (ov > 0.0) acc[p] = __builtin_fma(ov, gk, acc[p]);
+          if (e1 > y + 1.0) break;  // the bin continues into the next pixel
+          if (++kb < k.n_out) {
+            e0 = e1;
+            e1 = bin_edge(a, k, kb + 1);
+            gk = (double)gload(kb) * k.inv_q;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+    if (p < cnt) out(p, acc[p]);
+}
+
+// LDS of the backward when the taps fit one block: the binning adjoint of the
+// tile's staged pixels (FP32, planes as in the forward), the taps, and the
+// skewer's bin gradients when there are at most kInsBwdBins of them.
+constexpr int kInsBwdBins = 4096;
+struct InsBwdShared {
+  float f[8 * kDmaRows];
+  double h[kInsTapBlock];
+  double red[kInsThreads / 64];
+  float gb[kInsBwdBins];
+};
+
+// Copy of g[0 .. n_out) into LDS, 64 values per wave instruction
+// (global_load_lds; lanes past the end reload the last value).
+__device__ inline void bins_dma(const float *g, int64_t n_out, float *gb) {
+  const int lane = threadIdx.x & 63;
+  const int nch = (int)((n_out + 63) >> 6);
+  for (int c = threadIdx.x >> 6; c < nch; c += kInsThreads / 64) {
+    const int64_t j = min<int64_t>(64 * (int64_t)c + lane, n_out - 1);
+    __builtin_amdgcn_global_load_lds(g + j, gb + 64 * c, 4, 0, 0);
+  }
+}
+union InsBwdLds {
+  InsShared w;     // wide line-spread functions
+  InsBwdShared d;  // taps in one block
+};
+
+// Backward: the adjoint of the binning at the tile's staged pixels, then the
+// same line-spread convolution (the taps are even, so the adjoint convolves
+// with them too).  Taps in one block: each thread forms the binning adjoint of
+// eight consecutive staged pixels (one row of the eight planes) by the merge
+// walk; wider line-spread functions form it pixel by pixel, block by block.
 __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
     InsArgs a, const int2 *__restrict__ items) {
-  __shared__ InsShared sh;
+  __shared__ InsBwdLds lds;
   const int2 item = items[blockIdx.x];
   const InsSkewer k = ins_skewer(a, item.x);
   if (!k.ok) {
@@ -552,36 +649,66 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
     for (int t = threadIdx.x; t < span; t += kInsThreads) gF[p0 + t] = 0.0f;
     return;
   }
-  const int64_t n = k.n;
-  const double nd = (double)n;
-  const double x_first = bin_edge(a, k, 0), x_last = bin_edge(a, k, k.n_out);
+  InsBinGeom G;
+  G.nd = (double)(int)k.n;
+  G.inv_nd = 1.0 / G.nd;
+  G.x_first = bin_edge(a, k, 0);
+  G.x_last = bin_edge(a, k, k.n_out);
   const float *g = a.in + k.out_off;
-  const int64_t base = wrap_index(p0 - k.M, n);
-  // gradient reaching convolved pixel i (0 <= i < n) from the bins over it
-  const auto src = [&](int x) -> double {
-    int64_t i = base + x;
-    if (i >= n) i -= n;
-    if (i >= n) i %= n;
-    double v = 0.0;
-    // images y = i + L n of the pixel that meet [x_first, x_last)
-    const double L_lo = ceil((x_first - (double)i - 1.0) / nd);
-    const double L_hi = floor((x_last - (double)i) / nd);
-    for (double L = L_lo; L <= L_hi; L += 1.0) {
-      const double y = (double)i + L * nd;
-      int64_t kb = (int64_t)floor((y - x_first) * k.inv_q) - 1;
-      if (kb < 0) kb = 0;
-      for (; kb < k.n_out; ++kb) {
-        const double e0 = bin_edge(a, k, kb);
-        if (e0 >= y + 1.0) break;
-        const double e1 = bin_edge(a, k, kb + 1);
-        const double ov = fmin(y + 1.0, e1) - fmax(y, e0);
-        if (ov > 0.0) v += ov * (double)g[kb] * k.inv_q;
-      }
-    }
-    return v;
-  };
+  const auto g_global = [&](int64_t kb) -> float { return g[kb]; };
+  const uint32_t n32 = (uint32_t)k.n;
+  const uint32_t base = (uint32_t)wrap_index(p0 - k.M, (int)k.n);
+  const int T = 2 * k.M + 1;
   double acc[kInsPerLane];
-  const double Z = convolve_tile<false>(a, k, span, src, acc, sh);
+  double Z;
+  if (T <= kInsTapBlock) {
+    InsBwdShared &d = lds.d;
+    const int tbp = (T + 15) & ~15;
+    const bool lds_g = k.n_out <= kInsBwdBins;
+    if (lds_g) bins_dma(g, k.n_out, d.gb);  // in flight while the taps are formed
+    const double z_part = stage_taps(a, k, 0, T, tbp, d.h);
+    if (lds_g) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // every wave's copy is complete
+    const int rows = (span + tbp - 1 + 7) >> 3;  // staged offsets read by outputs < span
+    const auto stage_row = [&](auto gload) {
+      for (int r = threadIdx.x; r < rows; r += kInsThreads) {
+        // staged offsets 8r .. 8r + 7 are pixels (base + x) mod n, consecutive
+        // up to the end of the box
+        uint32_t i = base + 8u * (uint32_t)r;
+        if (i >= n32) i -= n32;
+        if (i >= n32) i %= n32;
+        int done = 0;
+        while (done < 8) {
+          const int c = min(8 - done, (int)(n32 - i));
+          const int x0 = 8 * r + done;
+          bin_adjoint_run(a, k, G, (int64_t)i, c, gload, [&](int p, double v) {
+            const int x = x0 + p;
+            d.f[(x & 7) * kDmaRows + (x >> 3)] = (float)v;
+          });
+          done += c;
+          i = 0;
+        }
+      }
+    };
+    if (lds_g)
+      stage_row([&](int64_t kb) -> float { return d.gb[kb]; });
+    else
+      stage_row(g_global);
+    Z = block_sum_d(z_part, d.red);  // its barriers publish the staged values and the taps
+#pragma unroll
+    for (int q = 0; q < kInsPerLane; ++q) acc[q] = 0.0;
+    if ((int)(threadIdx.x & ~63u) * kInsPerLane < span) conv_block_f32(tbp, acc, d.f, d.h);
+  } else {
+    const auto src = [&](int x) -> double {
+      uint32_t i = base + (uint32_t)x;
+      if (i >= n32) i -= n32;
+      if (i >= n32) i %= n32;
+      double v = 0.0;
+      bin_adjoint_run(a, k, G, (int64_t)i, 1, g_global, [&](int, double h) { v = h; });
+      return v;
+    };
+    Z = convolve_tile<false>(a, k, span, src, acc, lds.w);
+  }
   const double invZ = 1.0 / Z;
   const int t0 = threadIdx.x * kInsPerLane;
 #pragma unroll
@@ -600,10 +727,10 @@ int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward) {
 hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items, bool backward,
                              hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  if (backward)
+  if (backward) {
     hipLaunchKernelGGL(instrument_backward_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0,
                        st, a, items);
-  else {
+  } else {
     hipLaunchKernelGGL(instrument_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0, st, a,
                        items);
   }

@@ -11,6 +11,7 @@ import pytest
 from gpu_util import (OnDevice, assert_F_close, assert_mean_flux_root, assert_subset_flux,
                       assert_tau_close, gpu_normalise, gpu_tau, A_REL)
 from oracle import oracle as O
+from paper_1105_4747_amd import lyaf as L
 from synth import fields
 
 pytestmark = pytest.mark.gpu
@@ -28,7 +29,7 @@ def ragged_mix(seed=41, S=24):
                                   6.0, seed=seed)
 
 
-@pytest.mark.parametrize("shape", range(4))
+@pytest.mark.parametrize("shape", range(L.NUM_SHAPES))
 @pytest.mark.parametrize("persistent", [False, True])
 def test_every_shape_and_launch_form(shape, persistent):
     from paper_1105_4747_amd import lyaf as L
@@ -98,7 +99,7 @@ def test_autotune_times_every_candidate_and_caches(tmp_path, monkeypatch):
     info = p.describe()
     print(f"case: autotune {info}", flush=True)
     assert info["tuned"] and not info["from_cache"] and info["graph"]
-    assert len(info["timings_us"]) == 8
+    assert len(info["timings_us"]) == 2 * L.NUM_SHAPES
     lines = open(tmp_path / "tune.txt").read().split("\n")
     assert lines[0].startswith(info["key"] + " ")
     raw_ref = oracle_tau(w)
