@@ -113,18 +113,41 @@ __global__ __launch_bounds__(256) void reach_kernel(Batch b) {
     const float b_piv =
         (float)(kBeta * sqrt((double)T0 * pow((double)b.pivot, (double)K.gm1)) * (1.0 + 1e-6));
     float mv = 0.f;
-    int j = threadIdx.x;
-    for (; j + 3 * (int)blockDim.x < n; j += 4 * (int)blockDim.x) {  // four reads in flight
-      const float v0 = b.vpec[off + j], v1 = b.vpec[off + j + blockDim.x];
-      const float v2 = b.vpec[off + j + 2 * blockDim.x], v3 = b.vpec[off + j + 3 * blockDim.x];
-      mv = fmaxf(mv, fmaxf(fmaxf(fabsf(v0), fabsf(v1)), fmaxf(fabsf(v2), fabsf(v3))));
-      if (!isfinite(v0 + v1 + v2 + v3)) bad = 1;
-    }
-    for (; j < n; j += blockDim.x) {
-      const float v = b.vpec[off + j];
+    const float *vp = b.vpec + off;
+    auto one = [&](const float v) {
       mv = fmaxf(mv, fabsf(v));
       if (!isfinite(v)) bad = 1;
+    };
+    // float4 reads from the first 16-byte boundary, four in flight per thread
+    // (a 4096-pixel skewer in one round); the few values before and after
+    // are read one by one
+    const int head =
+        (int)min<int64_t>(n, (int64_t)(((16u - (reinterpret_cast<uintptr_t>(vp) & 15u)) & 15u) >> 2));
+    const int n4 = (n - head) >> 2;
+    const float4 *v4 = reinterpret_cast<const float4 *>(vp + head);
+    const int bd = (int)blockDim.x;
+    int j = threadIdx.x;
+    for (; j + 3 * bd < n4; j += 4 * bd) {
+      float4 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = v4[j + u * bd];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        one(q[u].x);
+        one(q[u].y);
+        one(q[u].z);
+        one(q[u].w);
+      }
     }
+    for (; j < n4; j += bd) {
+      const float4 q = v4[j];
+      one(q.x);
+      one(q.y);
+      one(q.z);
+      one(q.w);
+    }
+    if ((int)threadIdx.x < head) one(vp[threadIdx.x]);
+    for (int t = head + 4 * n4 + (int)threadIdx.x; t < n; t += bd) one(vp[t]);
     if (n > 0) mr = (mv + b.window_k * b_piv) * K.inv_dv;
   } else {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
