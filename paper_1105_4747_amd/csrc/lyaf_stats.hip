@@ -193,9 +193,25 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
   }
   double2 *buf = lds_ps;
   const float *f = F + off;
-  for (int j = threadIdx.x; j < M; j += kPsThreads)
-    buf[j] = make_double2(__builtin_fma((double)f[2 * j], inv_mean, -1.0),
-                          __builtin_fma((double)f[2 * j + 1], inv_mean, -1.0));
+  const auto put = [&](int j, float2 v) {
+    buf[j] = make_double2(__builtin_fma((double)v.x, inv_mean, -1.0),
+                          __builtin_fma((double)v.y, inv_mean, -1.0));
+  };
+  if ((reinterpret_cast<uintptr_t>(f) & 7u) == 0) {
+    // pairs of values as float2, four reads in flight per thread
+    const float2 *f2 = reinterpret_cast<const float2 *>(f);
+    int j = threadIdx.x;
+    for (; j + 3 * kPsThreads < M; j += 4 * kPsThreads) {
+      float2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = f2[j + u * kPsThreads];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) put(j + u * kPsThreads, v[u]);
+    }
+    for (; j < M; j += kPsThreads) put(j, f2[j]);
+  } else {
+    for (int j = threadIdx.x; j < M; j += kPsThreads) put(j, make_float2(f[2 * j], f[2 * j + 1]));
+  }
   __syncthreads();
   int Ns = 1;
   while (Ns * 8 <= M) {
@@ -214,7 +230,7 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
   const double2 half_step = make_double2(c1, s1);
   const double scale = dvs / (double)N;
   float *out = P + mode_off[s];
-  for (int m = threadIdx.x; m <= M; m += kPsThreads) {
+  const auto mode = [&](int m, double2 t) {  // t: table entry (m >> 1) of this transform
     const double2 zm = buf[m == M ? 0 : m];
     const double2 zr = buf[m == 0 ? 0 : M - m];
     const double2 zc = make_double2(zr.x, -zr.y);
@@ -225,12 +241,23 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
     if (m == M)
       tw = make_double2(-1.0, 0.0);
     else if ((m & 1) == 0)
-      tw = Tg[(m >> 1) * (kTwMax / M)];
+      tw = t;
     else
-      tw = cmul(Tg[(m >> 1) * (kTwMax / M)], half_step);
+      tw = cmul(t, half_step);
     const double2 X = cadd(E, cmul(tw, O));
     out[m] = (float)(scale * __builtin_fma(X.x, X.x, X.y * X.y));
+  };
+  // table reads of four modes in flight per thread (entry 0 stands in at m = M)
+  const auto entry = [&](int m) { return Tg[m == M ? 0 : (m >> 1) * (kTwMax / M)]; };
+  int m = threadIdx.x;
+  for (; m + 3 * kPsThreads <= M; m += 4 * kPsThreads) {
+    double2 t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = entry(m + u * kPsThreads);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mode(m + u * kPsThreads, t[u]);
   }
+  for (; m <= M; m += kPsThreads) mode(m, entry(m));
 }
 
 }  // namespace

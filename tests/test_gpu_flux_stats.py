@@ -148,3 +148,23 @@ def test_power_full_size_sampled(name):
         want, _ = FS.flux_power(Fh[a:b].astype(np.float64), [0, b - a], float(w.dv[s]),
                                 w.target_F)
         assert_power_close(got[mo[s]:mo[s + 1]], want, [0, b - a], f"{w.name} skewer {s}")
+
+
+def test_power_unaligned_flux_and_short_skewers():
+    """Flux that starts 4 bytes past an 8-byte boundary (the library then reads
+    it value by value) and skewers of every power-of-two length from 2 to 8192,
+    whose offsets leave the later skewers at odd multiples of 2 values."""
+    import torch
+    lens = [2 ** k for k in range(1, 14)] + [2, 4, 8]
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    rng = np.random.default_rng(17)
+    F = np.exp(-rng.exponential(0.4, int(offsets[-1]))).astype(np.float32)
+    dv = rng.uniform(1.0, 4.0, len(lens)).astype(np.float32)
+    want, _ = FS.flux_power(F.astype(np.float64), offsets, dv.astype(np.float64), 0.7)
+    for shift in (0, 1):
+        print(f"case: power, {len(lens)} skewers of 2..8192 px, flux shifted by {shift} value",
+              flush=True)
+        base = torch.zeros(int(offsets[-1]) + 2, device="cuda:0", dtype=torch.float32)
+        base[shift:shift + int(offsets[-1])] = to_dev(F)
+        got = gpu_power(base[shift:shift + int(offsets[-1])], dv, offsets, 0.7)
+        assert_power_close(got, want, offsets, f"shift {shift}")
