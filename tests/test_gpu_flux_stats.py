@@ -168,3 +168,20 @@ def test_power_unaligned_flux_and_short_skewers():
         base[shift:shift + int(offsets[-1])] = to_dev(F)
         got = gpu_power(base[shift:shift + int(offsets[-1])], dv, offsets, 0.7)
         assert_power_close(got, want, offsets, f"shift {shift}")
+
+
+def test_pdf_of_unaligned_flux():
+    """Flux that starts 0-3 values past a 16-byte boundary, with lengths that
+    leave a ragged end: the library reads whole 16-byte groups in between and
+    the values at either end one by one."""
+    import torch
+    rng = np.random.default_rng(23)
+    F = rng.uniform(-0.1, 1.1, 50003).astype(np.float32)
+    F[::97] = np.nan
+    for shift in range(4):
+        for n in (0, 1, 5, 4099, 50003 - shift):
+            print(f"case: pdf of {n} values at offset {shift}", flush=True)
+            base = torch.zeros(50008, device="cuda:0", dtype=torch.float32)
+            base[shift:shift + n] = to_dev(F[:n])
+            got = gpu_pdf(base[shift:shift + n])
+            assert np.array_equal(got, FS.flux_pdf(F[:n])), (shift, n)
