@@ -199,10 +199,8 @@ __device__ inline void conv_block(int tbp, double (&acc)[kInsPerLane], const Ins
 // Convolution of a tile: acc[q] = sum_{u < T} h_u src(8l + q + u) for the lane's
 // outputs t = 8l + q < span, taps in blocks of kInsTapBlock (unnormalised; the
 // sum of the taps is returned).  src(x) yields the value at staged offset x
-// (x = 0 .. span + T - 2).  With kBatchLoads, src is cheap and valid for any
-// x >= 0 (its reads stay in bounds), and each thread issues all its staging
-// reads before it stores any, so their latencies overlap.
-template <bool kBatchLoads, class Src>
+// (x = 0 .. span + T - 2).
+template <class Src>
 __device__ double convolve_tile(const InsArgs &a, const InsSkewer &k, int span, Src src,
                                 double (&acc)[kInsPerLane], InsShared &sh) {
   const int T = 2 * k.M + 1;
@@ -218,24 +216,7 @@ __device__ double convolve_tile(const InsArgs &a, const InsSkewer &k, int span, 
     z_part += stage_taps(a, k, u0, tb, tbp, sh.h);
     const int need = span + tbp - 1;  // staged offsets read by outputs < span
     const int real = span + tb - 1;   // offsets carrying real taps
-    if constexpr (kBatchLoads) {
-      constexpr int kIt = (kInsTile + kInsTapBlock + kInsThreads - 1) / kInsThreads;
-      using V = decltype(src(0));
-      V v[kIt];
-#pragma unroll
-      for (int j = 0; j < kIt; ++j) {
-        const int x = tid + j * kInsThreads;
-        const V y = src(u0 + x);
-        v[j] = x < real ? y : V(0);
-      }
-#pragma unroll
-      for (int j = 0; j < kIt; ++j) {
-        const int x = tid + j * kInsThreads;
-        if (x < need) stage_store(sh, x, (double)v[j]);
-      }
-    } else {
-      for (int x = tid; x < need; x += kInsThreads) stage_store(sh, x, x < real ? src(u0 + x) : 0.0);
-    }
+    for (int x = tid; x < need; x += kInsThreads) stage_store(sh, x, x < real ? src(u0 + x) : 0.0);
     __syncthreads();
     if (wave_active) conv_block(tbp, acc, sh);
   }
@@ -296,7 +277,6 @@ __device__ InsTile ins_tile(const InsArgs &a, const InsSkewer &k, int c, const I
   return t;
 }
 
-constexpr int kStageIt = (kInsTile + kInsTapBlock + kInsThreads - 1) / kInsThreads;  // 10
 constexpr int kNzPre = 4;  // noise draws per thread read ahead
 
 // Staged offset x of a tile holds pixel (p0 - M + x) mod n; n <= 2^24, so 32
@@ -306,30 +286,6 @@ __device__ inline float tile_flux(const float *F, uint32_t n32, uint32_t base, i
   if (i >= n32) i -= n32;
   if (i >= n32) i %= n32;
   return F[i];
-}
-
-// Reads of a tile whose taps fit one block, into registers: thread t holds
-// staged offsets t + 256 j (zero past the real ones).
-__device__ inline void tile_loads(const float *F, uint32_t n32, const InsTile &t, int T,
-                                  float (&v)[kStageIt]) {
-  const int real = t.span + T - 1;
-  if (n32 >= (uint32_t)(kStageIt * kInsThreads)) {
-    // the staged offsets wrap around the box at most once
-    uint32_t i = t.base + threadIdx.x;
-    if (i >= n32) i -= n32;
-#pragma unroll
-    for (int j = 0; j < kStageIt; ++j) {
-      v[j] = (int)threadIdx.x + j * kInsThreads < real ? F[i] : 0.0f;
-      i += kInsThreads;
-      if (i >= n32) i -= n32;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kStageIt; ++j) {
-      const int x = (int)threadIdx.x + j * kInsThreads;
-      v[j] = x < real ? tile_flux(F, n32, t.base, x) : 0.0f;
-    }
-  }
 }
 
 // Thread t writes the bins j0 .. j0 + cnt - 1 of a tile (consecutive, so that
@@ -498,7 +454,7 @@ __global__ __launch_bounds__(kInsThreads) __attribute__((amdgpu_waves_per_eu(4))
       const uint32_t base = t.base;
       const auto src = [&](int x) -> double { return (double)tile_flux(F, n32, base, x); };
       double acc[kInsPerLane];
-      const double Z = convolve_tile<false>(a, k, t.span, src, acc, sh);
+      const double Z = convolve_tile(a, k, t.span, src, acc, sh);
       finish_tile(a, k, t, acc, Z, nz, sh.s, sh.red);
       const InsTile tn = ins_tile(a, k, c + 1, &t);
       t = tn;
@@ -707,7 +663,7 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
       bin_adjoint_run(a, k, G, (int64_t)i, 1, g_global, [&](int, double h) { v = h; });
       return v;
     };
-    Z = convolve_tile<false>(a, k, span, src, acc, lds.w);
+    Z = convolve_tile(a, k, span, src, acc, lds.w);
   }
   const double invZ = 1.0 / Z;
   const int t0 = threadIdx.x * kInsPerLane;
