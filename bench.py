@@ -357,8 +357,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; --gpus N > 1 is not "
-                          "supported (skewers are independent: a batch shards by whole skewers, with one "
-                          "all-reduce of the mean-flux sums per root-find pass)"}))
+                          "supported (skewers are independent: a batch shards by whole "
+                          "skewers, with one all-reduce of the mean-flux sums per "
+                          "root-find pass)"}))
         sys.exit(2)
 
     import torch
