@@ -181,6 +181,45 @@ int oracle_tau(int64_t n_skewers, const int64_t *offsets, const double *delta,
   return ORC_OK;
 }
 
+/* Optical depth, eq. (6), at chosen pixels of one skewer: the full sum of
+ * oracle_tau with window_k = 0 (same terms, same order), for skewers too long
+ * for an all-pixel O(N^2) pass.  tau_out[t] = tau of pixel targets[t]
+ * (0 <= targets[t] < N) of skewer s; the targets are spread over threads. */
+int oracle_tau_at(int64_t n_skewers, const int64_t *offsets, const double *delta,
+                  const double *vpec, const double *dv, const double *T0,
+                  const double *gamma, double tau_ref, double delta_pivot,
+                  int64_t s, const int64_t *targets, int64_t n_targets,
+                  double *tau_out) {
+  int rc = check_skewers(n_skewers, offsets, delta, vpec, dv, T0, gamma,
+                         tau_ref, delta_pivot);
+  if (rc) return rc;
+  if (s < 0 || s >= n_skewers || n_targets < 0) return ORC_EINVAL;
+  const int64_t off = offsets[s];
+  const int64_t N = offsets[s + 1] - off;
+  for (int64_t t = 0; t < n_targets; ++t)
+    if (targets[t] < 0 || targets[t] >= N) return ORC_EINVAL;
+  const double V = (double)N * dv[s];
+  orc_src *src = (orc_src *)malloc((size_t)(N > 0 ? N : 1) * sizeof(orc_src));
+  if (!src) return ORC_EINVAL;
+  for (int64_t j = 0; j < N; ++j)
+    src[j] = source_params(delta[off + j], dv[s], T0[s], gamma[s], tau_ref,
+                           delta_pivot);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t t = 0; t < n_targets; ++t) {
+    const int64_t i = targets[t];
+    orc_acc acc = {0.0, 0.0};
+    for (int64_t j = 0; j < N; ++j) {
+      if (src[j].w == 0.0) continue;
+      double d = oracle_min_image((double)(i - j) * dv[s] - vpec[off + j], V);
+      double x = d / src[j].b;
+      acc_add(&acc, src[j].w * exp(-x * x));
+    }
+    tau_out[t] = acc_val(&acc);
+  }
+  free(src);
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Mean-flux normalisation (Sec. 2.3, last paragraph).
  * g(A) = (1/P) sum_p exp(-A tau_p) - Fbar is strictly decreasing in A when some

@@ -18,6 +18,8 @@ Parity status of each function (what pins it is listed in the tests):
                           shift / reflection / bulk-velocity equivariance,
                           40-digit brute force over the full image lattice.
   tau (windowed, k >= 8)  pinned against the full sum.
+  tau_at (chosen pixels)  the full sum at chosen pixels of one skewer; pinned
+                          bitwise against tau (full sum) on a ragged batch.
   mean_flux_A             pinned: uniform-tau closed form, two-level closed form,
                           scipy brentq, the printed <F> = 0.72 <-> tau_eff = 0.329.
   tau_grad, normalise_backward
@@ -88,6 +90,9 @@ def _load():
         pi64 = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_tau.argtypes = [i64, pi64, pd, pd, pd, pd, pd, dbl, dbl, dbl, pd]
         lib.oracle_tau.restype = i32
+        lib.oracle_tau_at.argtypes = [i64, pi64, pd, pd, pd, pd, pd, dbl, dbl, i64, pi64, i64,
+                                      pd]
+        lib.oracle_tau_at.restype = i32
         lib.oracle_mean_flux_A.argtypes = [i64, pd, dbl, pd, ctypes.POINTER(i32)]
         lib.oracle_mean_flux_A.restype = i32
         lib.oracle_finalise.argtypes = [i64, pd, dbl, pd, pd]
@@ -187,6 +192,26 @@ def tau(delta, vpec, dv, T0, gamma, offsets=None, n_skewers=None,
                             _p(out))
     if rc:
         raise OracleError(rc, "tau")
+    return out
+
+
+def tau_at(delta, vpec, dv, T0, gamma, offsets, skewer, targets, tau_ref=1.0,
+           delta_pivot=10.0):
+    """Raw optical depth of eq. (6) at the pixels ``targets`` of one skewer
+    (the full sum, as ``tau`` with window_k = 0; float64 [len(targets)])."""
+    delta, vpec = _d(delta).ravel(), _d(vpec).ravel()
+    P = delta.size
+    S = len(offsets) - 1
+    off = _offsets(S, P, offsets)
+    dv_, T0_, g_ = _per_skewer(dv, S), _per_skewer(T0, S), _per_skewer(gamma, S)
+    tg = np.ascontiguousarray(targets, np.int64)
+    out = np.empty(tg.size, np.float64)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    rc = _load().oracle_tau_at(S, off.ctypes.data_as(pi64), _p(delta), _p(vpec), _p(dv_),
+                               _p(T0_), _p(g_), float(tau_ref), float(delta_pivot),
+                               int(skewer), tg.ctypes.data_as(pi64), tg.size, _p(out))
+    if rc:
+        raise OracleError(rc, "tau_at")
     return out
 
 

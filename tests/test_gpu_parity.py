@@ -286,3 +286,25 @@ def test_config4_box_sampled():
     print(f"C4: worst tau err/tol {worst:.3f}, <F>-target {Fm - w.target_F:.2e}, "
           f"max|dF| {eF:.2e}")
     del d, raw, ts, F, A
+
+
+@pytest.mark.slow
+def test_tau_at_the_maximum_skewer_length():
+    """One skewer of 2^24 pixels, the longest the library accepts (pixel
+    offsets are formed exactly in FP32): 160 pixels, both ends (where the
+    minimal image wraps) and 128 drawn at random, against the oracle's full sum
+    at those pixels, and A as the root of the mean-flux condition on the GPU's
+    16.8M raw tau values."""
+    n = 1 << 24
+    w = fields.uniform_workload("1 x 2^24", 1, n, 2.0, 1.2, 2.0e4, 1.3, 0.75, 6.0, seed=9)
+    print(f"case: {w.name}", flush=True)
+    raw = gpu_tau(w)
+    ts, F, A = gpu_normalise(raw, w.target_F)
+    raw_np = raw.cpu().numpy()
+    pick = np.unique(np.r_[np.arange(16), np.arange(n - 16, n),
+                           np.random.default_rng(9).integers(0, n, 128)])
+    ref = O.tau_at(w.delta, w.vpec, w.dv, w.T0, w.gamma, w.offsets, 0, pick,
+                   tau_ref=w.tau_ref, delta_pivot=w.delta_pivot)
+    worst = assert_tau_close(raw_np[pick], ref, "2^24 sampled raw tau")
+    rA = assert_mean_flux_root(raw_np, float(A.cpu()), w.target_F, "2^24 A")
+    print(f"2^24: worst tau err/tol {worst:.3f}, root residual {rA:.2e} of A")

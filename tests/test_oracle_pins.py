@@ -410,3 +410,22 @@ def test_normalise_backward_against_fd():
     # frozen A: just A * G
     g0 = O.normalise_backward(tau, A, grad_F=cF, grad_tau_scaled=cT, implicit_A=False)
     np.testing.assert_allclose(g0, A * (cT - F * cF), rtol=1e-14)
+
+
+def test_tau_at_chosen_pixels_is_the_full_sum():
+    """tau_at evaluates the same full sum as tau for chosen pixels of one
+    skewer (same terms, same order): bitwise equal, including the first and
+    last pixels where the minimal image wraps, on a ragged batch."""
+    w = fields.ragged_workload("mix", 5, 40, 700, 1.0, 4.0, 1e4, 2.5e4, 1.1, 1.6, 1.0, 0.8, 6.0,
+                               seed=61)
+    full = O.tau(w.delta, w.vpec, w.dv, w.T0, w.gamma, offsets=w.offsets, tau_ref=w.tau_ref,
+                 delta_pivot=w.delta_pivot)
+    for s in range(w.n_skewers):
+        a, b = int(w.offsets[s]), int(w.offsets[s + 1])
+        pick = np.unique(np.r_[0, 1, b - a - 2, b - a - 1,
+                               np.random.default_rng(s).integers(0, b - a, 7)])
+        got = O.tau_at(w.delta, w.vpec, w.dv, w.T0, w.gamma, w.offsets, s, pick,
+                       tau_ref=w.tau_ref, delta_pivot=w.delta_pivot)
+        assert np.array_equal(got, full[a + pick])
+    with pytest.raises(O.OracleError):
+        O.tau_at(w.delta, w.vpec, w.dv, w.T0, w.gamma, w.offsets, 0, [int(np.diff(w.offsets)[0])])
