@@ -63,6 +63,9 @@ CASES = {
     "window-k-zero": ([600, 64], [2.0, 2.0], 170.0, 61.65, 10.0, 0.0, None),
     "taps-beyond-a-block": ([2500], [0.5], 224.0, 30.0, 3.0, 6.0, None),
     "no-convolution": ([300, 0, 90], [2.0, 2.0, 2.0], 0.0, 4.0, -1.0, 6.0, None),
+    # more than 4096 bins on one skewer: the adjoint reads the bin gradients from
+    # memory instead of its LDS copy
+    "many-bins": ([9000, 500], [2.0, 2.0], 7.0, 3.0826, 0.0, 6.0, None),
 }
 
 
