@@ -66,6 +66,9 @@ CASES = {
     # more than 4096 bins on one skewer: the adjoint reads the bin gradients from
     # memory instead of its LDS copy
     "many-bins": ([9000, 500], [2.0, 2.0], 7.0, 3.0826, 0.0, 6.0, None),
+    # boxes shorter than one thread's row of eight staged pixels (the row wraps
+    # around the box more than once)
+    "tiny-boxes": ([3, 5, 7, 1], [2.0, 2.0, 2.0, 2.0], 3.0, 1.5, -0.7, 6.0, None),
 }
 
 
