@@ -16,9 +16,11 @@
 // and has NS targets, H and NS uniform over the wave (from the lanes' window
 // bounds), so target minus source is the same on every lane and the four
 // targets of a step share t_k = t_0 + k a (a = dv r).  Short or wide skewers
-// sum over every target with the minimal image chosen per pair.  Per-skewer
-// T0/gamma terms are summed in FP64 per workgroup and then per skewer in a
-// fixed order.
+// sum over every target with the minimal image chosen per pair.  The three
+// per-source sums are FP32 blocks of 16 terms folded with Kahan compensation
+// (S1 is a signed sum that cancels across the line centre), Q_j is formed in
+// FP64 from them, and the per-skewer T0/gamma terms are summed in FP64 per
+// workgroup and then per skewer in a fixed order.
 #include <math.h>
 
 #include "lyaf_internal.h"
@@ -31,6 +33,18 @@ __device__ __forceinline__ float alog2(float x) { return __builtin_amdgcn_logf(x
 constexpr int kAdjThreads = 256;
 constexpr int kAdjTile = 256;  // sources per pass of the workgroup (one per thread)
 constexpr int kAdjMargin = 12; // staged targets beyond the reach
+
+// Compensated sum of FP32 blocks: sum + comp carries the running total.
+struct KahanSum {
+  float sum = 0.f, comp = 0.f;
+  __device__ __forceinline__ void add(const float blk) {
+    const float y = blk - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+  }
+  __device__ __forceinline__ float value() const { return sum - comp; }
+};
 
 __device__ __forceinline__ int adj_wave_max(int x) {
 #pragma unroll
@@ -69,7 +83,15 @@ __device__ void adjoint_pass(const Batch &b, const SkewerConst &K, int64_t off, 
   if (__any(valid && (!(delta >= 0.f) || !isfinite(delta))) && (threadIdx.x & 63) == 0)
     atomicOr(b.status, LYAF_STATUS_DOMAIN);
   const float dv = K.dv;
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // sums of g E, g E t, g E t^2
+  // sums of g E, g E t, g E t^2: blocks of 16 terms folded into Kahan sums
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+  KahanSum K0, K1, K2;
+  auto fold = [&]() {
+    K0.add(S0);
+    K1.add(S1);
+    K2.add(S2);
+    S0 = S1 = S2 = 0.f;
+  };
 
   // staged margin beyond the reach (window bounds are rounded outwards)
   const int RH = (R + kAdjMargin + 3) & ~3;
@@ -116,6 +138,7 @@ __device__ void adjoint_pass(const Batch &b, const SkewerConst &K, int64_t off, 
           S2 = __builtin_fmaf(gE, tt, S2);
         }
         fd += 4.f;
+        if ((st & 12) == 12) fold();  // every 4 steps (16 terms); st is wave-uniform
       }
     }
   } else {
@@ -140,24 +163,28 @@ __device__ void adjoint_pass(const Batch &b, const SkewerConst &K, int64_t off, 
         S1 += gEt;
         S2 = __builtin_fmaf(gEt, t, S2);
         fd += 1.f;
+        if ((c & 15) == 15) fold();
       }
+      fold();
     }
   }
+  fold();
 
   // per-source outputs (t = x sqrt(log2 e): x = t / sqrt(log2 e))
   if (valid) {
     float gd = 0.f, gv = 0.f;
     if (w > 0.f) {
       const float inv_s = (float)(1.0 / kSqrtLog2e);
-      const float s0 = w * S0;
-      const float s1 = w * S1 * inv_s;
-      const float s2 = w * S2 * (inv_s * inv_s);
-      const float Q = s2 - 1.2f * s0;
+      const float s0 = w * K0.value();
+      const float s1 = w * K1.value() * inv_s;
+      // Q = S2 - 1.2 S0 cancels where x^2 ~ 1.2: formed in FP64
+      const double Q =
+          (double)w * ((double)K2.value() * (1.0 / kLog2e) - 1.2 * (double)K0.value());
       gv = 2.f * s1 / bj;
       const float below = (delta <= b.pivot) ? 1.f : 0.f;
-      gd = (2.f * s0 + K.gm1 * below * Q) / delta;
-      q_T0 += (double)Q;
-      q_gam += (double)Q * ((double)l2D * kLn2);  // Q ln D
+      gd = (float)((2.0 * (double)s0 + (double)K.gm1 * below * Q) / (double)delta);
+      q_T0 += Q;
+      q_gam += Q * ((double)l2D * kLn2);  // Q ln D
     }
     gdelta[off + j] = gd;
     gvpec[off + j] = gv;

@@ -5,7 +5,8 @@ the FP64 oracle forward."""
 import numpy as np
 import pytest
 
-from gpu_util import OnDevice, assert_grad_close, gpu_normalise, gpu_tau, to_dev
+from gpu_util import (OnDevice, assert_grad_close, assert_per_skewer_close, gpu_normalise,
+                      gpu_tau, to_dev)
 from oracle import oracle as O
 from synth import fields
 
@@ -37,8 +38,8 @@ def test_tau_backward_random_cotangent():
                                 offsets=w.offsets)
     assert_grad_close(gd.cpu().numpy(), rd, "dL/dDelta")
     assert_grad_close(gv.cpu().numpy(), rv, "dL/dv")
-    assert_grad_close(gT.cpu().numpy(), rT, "dL/dT0")
-    assert_grad_close(gg.cpu().numpy(), rg, "dL/dgamma")
+    assert_per_skewer_close(gT.cpu().numpy(), rT, "dL/dT0")
+    assert_per_skewer_close(gg.cpu().numpy(), rg, "dL/dgamma")
 
 
 @pytest.mark.parametrize("n_pix,dv", [(256, 2.0), (40, 3.0)])
@@ -57,8 +58,8 @@ def test_tau_backward_full_box_path(n_pix, dv):
                                 offsets=w.offsets)
     assert_grad_close(gd.cpu().numpy(), rd, "dL/dDelta")
     assert_grad_close(gv.cpu().numpy(), rv, "dL/dv")
-    assert_grad_close(gT.cpu().numpy(), rT, "dL/dT0")
-    assert_grad_close(gg.cpu().numpy(), rg, "dL/dgamma")
+    assert_per_skewer_close(gT.cpu().numpy(), rT, "dL/dT0")
+    assert_per_skewer_close(gg.cpu().numpy(), rg, "dL/dgamma")
 
 
 def test_normalise_backward_against_oracle():
@@ -115,8 +116,8 @@ def test_autograd_config5_subset_against_oracle_and_fd():
     rd, rv, rT, rg = O.tau_grad(w.delta, w.vpec, w.dv, w.T0, w.gamma, g_raw, offsets=w.offsets)
     assert_grad_close(delta.grad.cpu().numpy(), rd, "dL/dDelta")
     assert_grad_close(vpec.grad.cpu().numpy(), rv, "dL/dv")
-    assert_grad_close(T0.grad.cpu().numpy(), rT, "dL/dT0")
-    assert_grad_close(gamma.grad.cpu().numpy(), rg, "dL/dgamma")
+    assert_per_skewer_close(T0.grad.cpu().numpy(), rT, "dL/dT0")
+    assert_per_skewer_close(gamma.grad.cpu().numpy(), rg, "dL/dgamma")
 
     # central FD of the oracle forward (A re-solved) along random directions
     def Lf(dd, vv, TT, gg):
@@ -174,6 +175,22 @@ def test_config5_full_size_sampled():
                                 offsets=sub.offsets)
     assert_grad_close(gd.cpu().numpy()[sel], rd, "dL/dDelta (sampled)")
     assert_grad_close(gv.cpu().numpy()[sel], rv, "dL/dv (sampled)")
-    assert_grad_close(gT.cpu().numpy()[pick], rT, "dL/dT0 (sampled)")
-    assert_grad_close(gg.cpu().numpy()[pick], rg, "dL/dgamma (sampled)")
+    assert_per_skewer_close(gT.cpu().numpy()[pick], rT, "dL/dT0 (sampled)")
+    assert_per_skewer_close(gg.cpu().numpy()[pick], rg, "dL/dgamma (sampled)")
+    # the adjoint alone on the same input: both sides take the oracle's
+    # dL/dtau_raw of the sampled skewers, rounded to float32
+    g32 = np.ascontiguousarray(g_ref[sel], np.float32)
+    ds = OnDevice(sub)
+    gd2, gv2 = torch.empty_like(ds.delta), torch.empty_like(ds.vpec)
+    gT2 = torch.empty(sub.n_skewers, device="cuda:0", dtype=torch.float64)
+    gg2 = torch.empty_like(gT2)
+    L.tau_backward(ds.delta, ds.vpec, ds.dv, ds.T0, ds.gamma, ds.offsets, to_dev(g32), gd2, gv2,
+                   gT2, gg2)
+    torch.cuda.synchronize()
+    rd2, rv2, rT2, rg2 = O.tau_grad(sub.delta, sub.vpec, sub.dv, sub.T0, sub.gamma,
+                                    g32.astype(np.float64), offsets=sub.offsets)
+    assert_grad_close(gd2.cpu().numpy(), rd2, "dL/dDelta (same input)")
+    assert_grad_close(gv2.cpu().numpy(), rv2, "dL/dv (same input)")
+    assert_per_skewer_close(gT2.cpu().numpy(), rT2, "dL/dT0 (same input)")
+    assert_per_skewer_close(gg2.cpu().numpy(), rg2, "dL/dgamma (same input)")
     del F_ref
