@@ -96,9 +96,12 @@ __global__ __launch_bounds__(256) void reach_kernel(Batch b) {
   {
     const double T0d = bad ? 1e4 : (double)T0, dvd = bad ? 1.0 : (double)dv;
     const double sq = sqrt(T0d);
+    const double R = kSqrtLog2e / (kBeta * sq);
+    K.R = (float)R;
+    // a line's integral over the pixels goes as w / r, so W is rounded
+    // together with the rounding of R: W / R is then off by one rounding
     K.W = (float)((double)b.tau_ref * pow(1e4, 0.7) * dvd / (kSqrtPi * kBeta) *
-                  pow(T0d, -1.2));
-    K.R = (float)(kSqrtLog2e / (kBeta * sq));
+                  pow(T0d, -1.2) * ((double)K.R / R));
     K.B = (float)(kBeta * sq);
     K.gm1 = bad ? 0.f : gm - 1.f;
     K.dv = (float)dvd;
