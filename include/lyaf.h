@@ -294,6 +294,25 @@ int lyaf_plan_destroy(lyaf_plan *plan);
  * bits accumulated since the last read. */
 int lyaf_status_read(void *stream, uint32_t *device_status);
 
+/* ---- kernel timing (measurement support) ----
+ *
+ * lyaf_kernel_timing(1) clears earlier records and starts recording: each
+ * launch site of the entry points then records a pair of HIP events on the
+ * caller's stream around its kernels, under one of the names
+ *   "reach"      the per-skewer constants and reach pass (lyaf_tau, lyaf_tau_backward)
+ *   "tau"        the windowed tau kernel of lyaf_tau (with the queue reset of a
+ *                persistent launch); "tau_plain" the plain full-sum kernels
+ *   "normalise", "normalise_backward", "tau_adjoint", "instrument",
+ *   "instrument_backward", "flux_pdf", "flux_power".
+ * Launches under stream capture (plans, caller graphs) are not recorded, and
+ * recording stops after 65536 launches.  lyaf_kernel_timing(0) stops and
+ * clears.  lyaf_kernel_timing_read waits for the recorded launches of `name`,
+ * writes the sum of their durations (ms) and their number, and drops those
+ * records.  Timing costs two event records per launch; it is off by default.
+ * Errors: EINVAL (NULL argument), EDEVICE. */
+int lyaf_kernel_timing(int enable);
+int lyaf_kernel_timing_read(const char *name, double *total_ms, int64_t *count);
+
 /* Human-readable name of a return code (static string). */
 const char *lyaf_strerror(int code);
 

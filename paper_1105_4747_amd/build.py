@@ -1,9 +1,12 @@
 """Build liblyaf.so (the library) and libpeaks.so (the rate microbenchmarks
 the benchmark reports against) for gfx950 with hipcc, in-tree next to this
-file."""
+file.  Beside each library a ``.srchash`` file records the SHA-256 of the
+sources it was built from; the binding refuses a library whose sources have
+changed since (content, not file times, which a copied tree may not keep)."""
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -28,14 +31,32 @@ FLAGS = [
 ]
 
 
+def source_hash(paths=None) -> str:
+    """SHA-256 over the library's sources and headers (names and contents)."""
+    h = hashlib.sha256()
+    for p in sorted(SOURCES + HEADERS if paths is None else paths):
+        h.update(os.path.relpath(p, ROOT).encode())
+        h.update(b"\0")
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def built_hash(lib: str = LIB):
+    """The source hash recorded when ``lib`` was built, or None."""
+    try:
+        with open(lib + ".srchash") as f:
+            return f.read().strip()
+    except OSError:
+        return None
+
+
 def needs_build() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS)
+    return not os.path.exists(LIB) or built_hash(LIB) != source_hash()
 
 
-def _hipcc(out: str, sources, verbose: bool) -> str:
+def _hipcc(out: str, sources, verbose: bool, deps=None) -> str:
+    digest = source_hash(deps if deps is not None else list(sources))
     tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, "-o", tmp, *sources]
     if verbose:
@@ -48,12 +69,15 @@ def _hipcc(out: str, sources, verbose: bool) -> str:
     if verbose and err.strip():
         print(err, file=sys.stderr)
     os.replace(tmp, out)
+    with open(out + ".srchash", "w") as f:
+        f.write(digest + "\n")
     return out
 
 
 def build(verbose: bool = False) -> str:
-    _hipcc(PEAKS_LIB, PEAKS_SOURCES, verbose)
-    return _hipcc(LIB, SOURCES, verbose)
+    _hipcc(PEAKS_LIB, PEAKS_SOURCES, verbose,
+           deps=PEAKS_SOURCES + [os.path.join(ROOT, "include", "lyaf_peaks.h")])
+    return _hipcc(LIB, SOURCES, verbose, deps=SOURCES + HEADERS)
 
 
 if __name__ == "__main__":

@@ -22,9 +22,12 @@ namespace {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
-// Host mirrors of the work list currently uploaded to a workspace.
+// A work list uploaded for one workspace and tile length: host mirrors, pinned
+// staging and the device copies.  The forward (1024-target tiles by default)
+// and the adjoint (512) keep one list each, so calls that alternate between
+// them reuse their lists without re-uploading or synchronising.
 struct HostPlan {
-  int tile = 0;                    // targets per work item of the uploaded list
+  int tile = 0;                    // targets per work item
   std::vector<int64_t> offsets;    // [S+1]
   std::vector<int64_t> item_base;  // [S+1]
   int64_t n_items = 0;
@@ -33,13 +36,64 @@ struct HostPlan {
   int2 *h_items = nullptr;
   int64_t *h_ib = nullptr;
   int64_t h_off_cap = 0, h_items_cap = 0, h_ib_cap = 0;
+  // device copies
+  int64_t *d_off = nullptr;
+  int2 *d_items = nullptr;
+  int64_t *d_ib = nullptr;
+  int64_t d_off_cap = 0, d_items_cap = 0, d_ib_cap = 0;
 };
-std::map<Workspace *, HostPlan> g_plans;
+std::map<std::pair<Workspace *, int>, HostPlan> g_plans;
 
 int map_err(hipError_t e) {
   if (e == hipSuccess) return LYAF_OK;
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return LYAF_ENOMEM;
   return LYAF_EDEVICE;
+}
+
+// Opt-in kernel timing (lyaf_kernel_timing): while enabled, each launch site
+// of the entry points records a pair of events around its kernels on the
+// caller's stream, under a name; reading a name sums the elapsed times of its
+// recorded pairs.  Launches under stream capture are not recorded.
+struct TimedLaunch {
+  std::string name;
+  hipEvent_t start, stop;
+};
+struct KernelTimer {
+  bool on = false;
+  std::vector<TimedLaunch> rec;
+  std::vector<hipEvent_t> pool;
+};
+KernelTimer g_kt;
+constexpr size_t kMaxTimedLaunches = 1 << 16;
+
+hipEvent_t timer_event() {
+  if (!g_kt.pool.empty()) {
+    hipEvent_t e = g_kt.pool.back();
+    g_kt.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+template <typename F>
+hipError_t timed(const char *name, hipStream_t st, F &&launch) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!g_kt.on || g_kt.rec.size() >= kMaxTimedLaunches ||
+      hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return launch();
+  hipEvent_t a = timer_event(), b = timer_event();
+  if (!a || !b) {
+    if (a) g_kt.pool.push_back(a);
+    if (b) g_kt.pool.push_back(b);
+    return launch();
+  }
+  hipError_t e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, st)) != hipSuccess) return e;
+  g_kt.rec.push_back({name, a, b});
+  return hipSuccess;
 }
 
 template <typename T>
@@ -134,7 +188,7 @@ int check_args(const lyaf_skewers *sk, const lyaf_params *prm, int64_t *P_out) {
 // Upload offsets, the (skewer, tile) work list and the per-skewer first item,
 // unless the workspace already holds this exact set of offsets.
 int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out) {
-  HostPlan &hp = g_plans[ws];
+  HostPlan &hp = g_plans[std::make_pair(ws, tile)];
   *out = &hp;
   const int64_t S = sk->n_skewers;
   if (hp.tile == tile && (int64_t)hp.offsets.size() == S + 1 &&
@@ -156,9 +210,9 @@ int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out)
   if ((e = grow_host(hp.h_off, hp.h_off_cap, S + 1)) != hipSuccess ||
       (e = grow_host(hp.h_ib, hp.h_ib_cap, S + 1)) != hipSuccess ||
       (e = grow_host(hp.h_items, hp.h_items_cap, ni)) != hipSuccess ||
-      (e = grow_dev(ws->offsets, ws->off_cap, S + 1)) != hipSuccess ||
-      (e = grow_dev(ws->item_base, ws->ib_cap, S + 1)) != hipSuccess ||
-      (e = grow_dev(ws->items, ws->items_cap, ni)) != hipSuccess ||
+      (e = grow_dev(hp.d_off, hp.d_off_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(hp.d_ib, hp.d_ib_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(hp.d_items, hp.d_items_cap, ni)) != hipSuccess ||
       (e = grow_dev(ws->skc, ws->skc_cap, S)) != hipSuccess) {
     hp.offsets.clear();
     return map_err(e);
@@ -170,11 +224,11 @@ int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out)
     for (int64_t t = 0; t < nt; ++t)
       hp.h_items[hp.item_base[s] + t] = make_int2((int)s, (int)t);
   }
-  if ((e = hipMemcpyAsync(ws->offsets, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
+  if ((e = hipMemcpyAsync(hp.d_off, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(ws->item_base, hp.h_ib, sizeof(int64_t) * (size_t)(S + 1),
+      (e = hipMemcpyAsync(hp.d_ib, hp.h_ib, sizeof(int64_t) * (size_t)(S + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
-      (ni > 0 && (e = hipMemcpyAsync(ws->items, hp.h_items, sizeof(int2) * (size_t)ni,
+      (ni > 0 && (e = hipMemcpyAsync(hp.d_items, hp.h_items, sizeof(int2) * (size_t)ni,
                                      hipMemcpyHostToDevice, ws->stream)) != hipSuccess)) {
     hp.offsets.clear();
     return map_err(e);
@@ -182,16 +236,20 @@ int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out)
   return LYAF_OK;
 }
 
-// Host mirror of the instrument work list uploaded to a workspace.
+// The instrument work list uploaded for one workspace and direction (forward:
+// one item per skewer with bins; backward: one per pixel tile), with its device
+// copies.
 struct HostInsPlan {
-  bool backward = false;
   std::vector<int64_t> offsets, out_offsets;  // [S+1] each
   int64_t n_items = 0;
   int64_t *h_off = nullptr, *h_oo = nullptr;
   int2 *h_items = nullptr;
   int64_t h_off_cap = 0, h_oo_cap = 0, h_items_cap = 0;
+  int64_t *d_off = nullptr, *d_oo = nullptr;
+  int2 *d_items = nullptr;
+  int64_t d_off_cap = 0, d_oo_cap = 0, d_items_cap = 0;
 };
-std::map<Workspace *, HostInsPlan> g_ins_plans;
+std::map<std::pair<Workspace *, bool>, HostInsPlan> g_ins_plans;
 
 int check_ins(int64_t S, const int64_t *offsets, const float *dv,
               const lyaf_instrument_params *ip, const int64_t *out_offsets, int64_t *P_out,
@@ -224,9 +282,9 @@ int check_ins(int64_t S, const int64_t *offsets, const float *dv,
 // unless the workspace already holds this exact list.
 int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int64_t *out_offsets,
                     bool backward, HostInsPlan **out) {
-  HostInsPlan &hp = g_ins_plans[ws];
+  HostInsPlan &hp = g_ins_plans[std::make_pair(ws, backward)];
   *out = &hp;
-  if (hp.backward == backward && (int64_t)hp.offsets.size() == S + 1 &&
+  if ((int64_t)hp.offsets.size() == S + 1 &&
       memcmp(hp.offsets.data(), offsets, sizeof(int64_t) * (size_t)(S + 1)) == 0 &&
       memcmp(hp.out_offsets.data(), out_offsets, sizeof(int64_t) * (size_t)(S + 1)) == 0)
     return LYAF_OK;
@@ -242,9 +300,9 @@ int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int6
   if ((e = grow_host(hp.h_off, hp.h_off_cap, S + 1)) != hipSuccess ||
       (e = grow_host(hp.h_oo, hp.h_oo_cap, S + 1)) != hipSuccess ||
       (e = grow_host(hp.h_items, hp.h_items_cap, ni)) != hipSuccess ||
-      (e = grow_dev(ws->ins_off, ws->ins_off_cap, S + 1)) != hipSuccess ||
-      (e = grow_dev(ws->ins_oo, ws->ins_oo_cap, S + 1)) != hipSuccess ||
-      (e = grow_dev(ws->ins_items, ws->ins_items_cap, ni)) != hipSuccess)
+      (e = grow_dev(hp.d_off, hp.d_off_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(hp.d_oo, hp.d_oo_cap, S + 1)) != hipSuccess ||
+      (e = grow_dev(hp.d_items, hp.d_items_cap, ni)) != hipSuccess)
     return map_err(e);
   memcpy(hp.h_off, offsets, sizeof(int64_t) * (size_t)(S + 1));
   memcpy(hp.h_oo, out_offsets, sizeof(int64_t) * (size_t)(S + 1));
@@ -254,14 +312,13 @@ int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int6
                                        out_offsets[s + 1] - out_offsets[s], backward);
     for (int t = 0; t < c; ++t) hp.h_items[k++] = make_int2((int)s, t);
   }
-  if ((e = hipMemcpyAsync(ws->ins_off, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
+  if ((e = hipMemcpyAsync(hp.d_off, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(ws->ins_oo, hp.h_oo, sizeof(int64_t) * (size_t)(S + 1),
+      (e = hipMemcpyAsync(hp.d_oo, hp.h_oo, sizeof(int64_t) * (size_t)(S + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
-      (ni > 0 && (e = hipMemcpyAsync(ws->ins_items, hp.h_items, sizeof(int2) * (size_t)ni,
+      (ni > 0 && (e = hipMemcpyAsync(hp.d_items, hp.h_items, sizeof(int2) * (size_t)ni,
                                      hipMemcpyHostToDevice, ws->stream)) != hipSuccess))
     return map_err(e);
-  hp.backward = backward;
   hp.offsets.assign(offsets, offsets + S + 1);
   hp.out_offsets.assign(out_offsets, out_offsets + S + 1);
   hp.n_items = ni;
@@ -309,10 +366,11 @@ int ensure_ps_plan(Workspace *ws, int64_t S, const int64_t *offsets, HostPsPlan 
   return LYAF_OK;
 }
 
-InsArgs make_ins_args(Workspace *ws, const float *dv, const lyaf_instrument_params *ip) {
+InsArgs make_ins_args(Workspace *ws, const HostInsPlan *hp, const float *dv,
+                      const lyaf_instrument_params *ip) {
   InsArgs a;
-  a.offsets = ws->ins_off;
-  a.out_offsets = ws->ins_oo;
+  a.offsets = hp->d_off;
+  a.out_offsets = hp->d_oo;
   a.dv = dv;
   a.in = nullptr;
   a.out = nullptr;
@@ -327,14 +385,16 @@ InsArgs make_ins_args(Workspace *ws, const float *dv, const lyaf_instrument_para
   return a;
 }
 
-Batch make_batch(const lyaf_skewers *sk, const lyaf_params *prm, Workspace *ws) {
+// offsets_dev: the device copy of the batch's offsets [S+1].
+Batch make_batch(const lyaf_skewers *sk, const lyaf_params *prm, Workspace *ws,
+                 const int64_t *offsets_dev) {
   Batch b;
   b.delta = sk->delta;
   b.vpec = sk->vpec;
   b.dv = sk->dv;
   b.T0 = sk->T0;
   b.gamma = sk->gamma;
-  b.offsets = ws->offsets;
+  b.offsets = offsets_dev;
   b.skc = ws->skc;
   b.n_skewers = sk->n_skewers;
   b.tau_ref = (float)prm->tau_ref;
@@ -380,25 +440,32 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out, voi
   const int variant = shape ? (int)shape - 1 : kTauVariantDefault;
   HostPlan *hp = nullptr;
   if ((rc = ensure_plan(ws, sk, kTauVariants[variant].tile, &hp))) return rc;
-  const Batch b = make_batch(sk, prm, ws);
-  hipError_t e = launch_reach(b, st);
+  const Batch b = make_batch(sk, prm, ws, hp->d_off);
+  hipError_t e = timed("reach", st, [&] { return launch_reach(b, st); });
   if (e != hipSuccess) return map_err(e);
   const int64_t S = sk->n_skewers;
   if (prm->flags & LYAF_FLAG_PLAIN) {
     for (int64_t s = 0; s < S && e == hipSuccess; ++s)
-      e = launch_tau_plain(b, s, hp->offsets[s + 1] - hp->offsets[s], tau_out, st);
+      e = timed("tau_plain", st, [&] {
+        return launch_tau_plain(b, s, hp->offsets[s + 1] - hp->offsets[s], tau_out, st);
+      });
   } else if (prm->flags & LYAF_FLAG_PER_SKEWER) {
     for (int64_t s = 0; s < S && e == hipSuccess; ++s)
-      e = launch_tau_window(b, ws->items + hp->item_base[s],
-                            hp->item_base[s + 1] - hp->item_base[s], tau_out, st, variant);
+      e = timed("tau", st, [&] {
+        return launch_tau_window(b, hp->d_items + hp->item_base[s],
+                                 hp->item_base[s + 1] - hp->item_base[s], tau_out, st, variant);
+      });
   } else if (prm->flags & LYAF_FLAG_PERSISTENT) {
     if (!ws->queue && (e = hipMalloc((void **)&ws->queue, sizeof(unsigned int))) != hipSuccess)
       return map_err(e);
     const int pg = tau_persistent_grid(variant);
     if (pg <= 0) return LYAF_EDEVICE;
-    e = launch_tau_window(b, ws->items, hp->n_items, tau_out, st, variant, pg, ws->queue);
+    e = timed("tau", st, [&] {
+      return launch_tau_window(b, hp->d_items, hp->n_items, tau_out, st, variant, pg, ws->queue);
+    });
   } else {
-    e = launch_tau_window(b, ws->items, hp->n_items, tau_out, st, variant);
+    e = timed("tau", st,
+              [&] { return launch_tau_window(b, hp->d_items, hp->n_items, tau_out, st, variant); });
   }
   return map_err(e);
 }
@@ -413,7 +480,9 @@ int lyaf_normalise_mean_flux(int64_t n_pix, float *tau_inout, float *F_out, doub
   Workspace *ws = nullptr;
   int rc = get_ws(st, &ws);
   if (rc) return rc;
-  return map_err(launch_norm(n_pix, tau_inout, F_out, target_F, A_dev, *ws, st));
+  return map_err(timed("normalise", st, [&] {
+    return launch_norm(n_pix, tau_inout, F_out, target_F, A_dev, *ws, st);
+  }));
 }
 
 int lyaf_normalise_mean_flux_backward(int64_t n_pix, const float *tau_raw, const double *A_dev,
@@ -427,8 +496,10 @@ int lyaf_normalise_mean_flux_backward(int64_t n_pix, const float *tau_raw, const
   Workspace *ws = nullptr;
   int rc = get_ws(st, &ws);
   if (rc) return rc;
-  return map_err(launch_norm_backward(n_pix, tau_raw, A_dev, grad_F, grad_tau_scaled,
-                                      implicit_A ? 1 : 0, grad_tau_raw_out, *ws, st));
+  return map_err(timed("normalise_backward", st, [&] {
+    return launch_norm_backward(n_pix, tau_raw, A_dev, grad_F, grad_tau_scaled,
+                                implicit_A ? 1 : 0, grad_tau_raw_out, *ws, st);
+  }));
 }
 
 int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm, const float *grad_tau_raw,
@@ -447,8 +518,9 @@ int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm, const floa
   if ((rc = ensure_plan(ws, sk, kTauTile, &hp))) return rc;
   hipError_t e = grow_dev(ws->gpart, ws->gpart_cap, 2 * std::max<int64_t>(hp->n_items, 1));
   if (e != hipSuccess) return map_err(e);
-  const Batch b = make_batch(sk, prm, ws);
-  if ((e = launch_reach(b, st)) != hipSuccess) return map_err(e);
+  const Batch b = make_batch(sk, prm, ws, hp->d_off);
+  if ((e = timed("reach", st, [&] { return launch_reach(b, st); })) != hipSuccess)
+    return map_err(e);
   if (hp->n_items == 0) {
     // every skewer is empty: the per-skewer sums are zero
     if (grad_T0 && (e = hipMemsetAsync(grad_T0, 0, sizeof(double) * (size_t)sk->n_skewers, st)))
@@ -458,8 +530,10 @@ int lyaf_tau_backward(const lyaf_skewers *sk, const lyaf_params *prm, const floa
       return map_err(e);
     return LYAF_OK;
   }
-  return map_err(launch_tau_adjoint(b, ws->items, hp->n_items, ws->item_base, grad_tau_raw,
-                                    grad_delta, grad_vpec, grad_T0, grad_gamma, ws->gpart, st));
+  return map_err(timed("tau_adjoint", st, [&] {
+    return launch_tau_adjoint(b, hp->d_items, hp->n_items, hp->d_ib, grad_tau_raw, grad_delta,
+                              grad_vpec, grad_T0, grad_gamma, ws->gpart, st);
+  }));
 }
 
 int lyaf_instrument(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
@@ -476,11 +550,12 @@ int lyaf_instrument(int64_t n_skewers, const int64_t *offsets, const float *dv, 
   if ((rc = get_ws(st, &ws))) return rc;
   HostInsPlan *hp = nullptr;
   if ((rc = ensure_ins_plan(ws, n_skewers, offsets, out_offsets, false, &hp))) return rc;
-  InsArgs a = make_ins_args(ws, dv, ip);
+  InsArgs a = make_ins_args(ws, hp, dv, ip);
   a.in = F;
   a.out = F_obs;
   a.noise = ip->noise_sigma > 0.0 ? noise : nullptr;
-  return map_err(launch_instrument(a, ws->ins_items, hp->n_items, false, st));
+  return map_err(timed("instrument", st,
+                       [&] { return launch_instrument(a, hp->d_items, hp->n_items, false, st); }));
 }
 
 int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const float *dv,
@@ -497,10 +572,11 @@ int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const fl
   if ((rc = get_ws(st, &ws))) return rc;
   HostInsPlan *hp = nullptr;
   if ((rc = ensure_ins_plan(ws, n_skewers, offsets, out_offsets, true, &hp))) return rc;
-  InsArgs a = make_ins_args(ws, dv, ip);
+  InsArgs a = make_ins_args(ws, hp, dv, ip);
   a.in = grad_obs;
   a.out = grad_F;
-  return map_err(launch_instrument(a, ws->ins_items, hp->n_items, true, st));
+  return map_err(timed("instrument_backward", st,
+                       [&] { return launch_instrument(a, hp->d_items, hp->n_items, true, st); }));
 }
 
 int lyaf_flux_pdf(int64_t n_pix, const float *F, int64_t *counts, void *stream) {
@@ -512,7 +588,8 @@ int lyaf_flux_pdf(int64_t n_pix, const float *F, int64_t *counts, void *stream) 
   if (rc) return rc;
   hipError_t e = grow_dev(ws->pdf_part, ws->pdf_part_cap, (int64_t)kPdfMaxBlocks * kPdfCountSlots);
   if (e != hipSuccess) return map_err(e);
-  return map_err(launch_flux_pdf(n_pix, F, ws->pdf_part, counts, st));
+  return map_err(
+      timed("flux_pdf", st, [&] { return launch_flux_pdf(n_pix, F, ws->pdf_part, counts, st); }));
 }
 
 int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
@@ -539,8 +616,10 @@ int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, 
     }
     if ((e = launch_twiddles(ws->ps_twiddle, st)) != hipSuccess) return map_err(e);
   }
-  return map_err(launch_flux_power(n_skewers, hp->max_n, F, ws->ps_off, ws->ps_mo, dv,
-                                   1.0 / mean_F, ws->ps_twiddle, power, ws->status, st));
+  return map_err(timed("flux_power", st, [&] {
+    return launch_flux_power(n_skewers, hp->max_n, F, ws->ps_off, ws->ps_mo, dv,
+                             1.0 / mean_F, ws->ps_twiddle, power, ws->status, st);
+  }));
 }
 
 double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {
@@ -549,6 +628,43 @@ double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {
 
 double lyaf_lya_lyb_path_kms(double proximity_kms) {
   return kSpeedOfLightKms * log(kLymanAlphaAngstrom / kLymanBetaAngstrom) - proximity_kms;
+}
+
+int lyaf_kernel_timing(int enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto &r : g_kt.rec) {
+    g_kt.pool.push_back(r.start);
+    g_kt.pool.push_back(r.stop);
+  }
+  g_kt.rec.clear();
+  g_kt.on = enable != 0;
+  return LYAF_OK;
+}
+
+int lyaf_kernel_timing_read(const char *name, double *total_ms, int64_t *count) {
+  if (!name || !total_ms || !count) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  double sum = 0.0;
+  int64_t n = 0;
+  std::vector<TimedLaunch> keep;
+  for (auto &r : g_kt.rec) {
+    if (r.name != name) {
+      keep.push_back(r);
+      continue;
+    }
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) return map_err(e);
+    sum += (double)ms;
+    ++n;
+    g_kt.pool.push_back(r.start);
+    g_kt.pool.push_back(r.stop);
+  }
+  g_kt.rec.swap(keep);
+  *total_ms = sum;
+  *count = n;
+  return LYAF_OK;
 }
 
 int lyaf_status_read(void *stream, uint32_t *device_status) {
@@ -656,7 +772,7 @@ void plan_free(lyaf_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   void *bufs[] = {p->items, p->queue, p->ws.status, p->ws.partials, p->ws.norm,
-                  p->ws.ratio, p->ws.skc, p->ws.offsets, p->ws.item_base};
+                  p->ws.ratio, p->ws.skc, p->ws.offsets};
   for (void *q : bufs)
     if (q) (void)hipFree(q);
   delete p;
@@ -697,7 +813,7 @@ hipError_t upload_items(lyaf_plan *p, const std::vector<int2> &items) {
   return hipMemcpy(p->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
 }
 
-Batch plan_batch(lyaf_plan *p) { return make_batch(&p->sk, &p->prm, &p->ws); }
+Batch plan_batch(lyaf_plan *p) { return make_batch(&p->sk, &p->prm, &p->ws, p->ws.offsets); }
 
 hipError_t enqueue_tau(lyaf_plan *p, hipStream_t st) {
   const Batch b = plan_batch(p);
@@ -715,13 +831,13 @@ hipError_t enqueue_forward(lyaf_plan *p, hipStream_t st) {
 
 std::string make_tune_key(const lyaf_plan *p) {
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return "v2|unknown";
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return "v3|unknown";
   const int64_t S = p->sk.n_skewers;
   const double meanN = S > 0 ? (double)p->P / (double)S : 0.0;
   int maxR = 0;
   for (const auto &k : p->skc_host) maxR = std::max(maxR, k.reach);
   char buf[512];
-  snprintf(buf, sizeof(buf), "v2|%s|cu%d|S2^%d|N2^%d|R2^%d|k%g", prop.gcnArchName,
+  snprintf(buf, sizeof(buf), "v3|%s|cu%d|S2^%d|N2^%d|R2^%d|k%g", prop.gcnArchName,
            prop.multiProcessorCount, (int)lround(log2((double)std::max<int64_t>(S, 1))),
            (int)lround(log2(std::max(meanN, 1.0))), (int)lround(log2(std::max(maxR, 1))),
            p->prm.window_k);
@@ -731,34 +847,64 @@ std::string make_tune_key(const lyaf_plan *p) {
   return k;
 }
 
-// Time the tau stage of every candidate on the plan's data (3 replays after
-// one warm-up each) and keep the fastest.
+// Time the tau stage of every candidate on the plan's data: after one warm-up,
+// kTuneReps replays each between its own pair of events, and the candidate's
+// time is their median.  The persistent launch is kept only when it beats the
+// best one-workgroup-per-item launch by more than kTuneMargin (its queue costs
+// atomics and a reset launch; within the noise the plain grid wins).
+constexpr int kTuneReps = 11;
+constexpr double kTuneMargin = 0.02;
+
 int autotune(lyaf_plan *p, hipStream_t st) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LYAF_EDEVICE;
-  Candidate best{-1, 0, 1e300};
-  for (int v = 0; v < kNumTauVariants; ++v) {
-    if (upload_items(p, build_items(p, kTauVariants[v].tile)) != hipSuccess) return LYAF_ENOMEM;
+  hipEvent_t ev[kTuneReps + 1] = {};
+  auto destroy = [&]() {
+    for (auto &x : ev)
+      if (x) (void)hipEventDestroy(x);
+  };
+  for (auto &x : ev)
+    if (hipEventCreate(&x) != hipSuccess) {
+      destroy();
+      return LYAF_EDEVICE;
+    }
+  Candidate best_grid{-1, 0, 1e300}, best_pers{-1, 1, 1e300};
+  int rc = LYAF_OK;
+  for (int v = 0; v < kNumTauVariants && rc == LYAF_OK; ++v) {
+    if (upload_items(p, build_items(p, kTauVariants[v].tile)) != hipSuccess) {
+      rc = LYAF_ENOMEM;
+      break;
+    }
     const int pg = tau_persistent_grid(v);
-    for (int ps = 0; ps < 2; ++ps) {
+    for (int ps = 0; ps < 2 && rc == LYAF_OK; ++ps) {
+      if (ps && pg <= 0) continue;
       p->variant = v;
       p->persistent_grid = ps ? pg : 0;
-      if (ps && pg <= 0) continue;
-      if (enqueue_tau(p, st) != hipSuccess) return LYAF_EDEVICE;
-      if (hipEventRecord(e0, st) != hipSuccess) return LYAF_EDEVICE;
-      for (int r = 0; r < 3; ++r)
-        if (enqueue_tau(p, st) != hipSuccess) return LYAF_EDEVICE;
-      float ms = 0.f;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-        return LYAF_EDEVICE;
-      const Candidate c{v, ps, 1e3 * (double)ms / 3.0};
+      bool ok = enqueue_tau(p, st) == hipSuccess && hipEventRecord(ev[0], st) == hipSuccess;
+      for (int r = 0; r < kTuneReps && ok; ++r)
+        ok = enqueue_tau(p, st) == hipSuccess && hipEventRecord(ev[r + 1], st) == hipSuccess;
+      ok = ok && hipEventSynchronize(ev[kTuneReps]) == hipSuccess;
+      double t[kTuneReps];
+      for (int r = 0; r < kTuneReps && ok; ++r) {
+        float ms = 0.f;
+        ok = hipEventElapsedTime(&ms, ev[r], ev[r + 1]) == hipSuccess;
+        t[r] = 1e3 * (double)ms;
+      }
+      if (!ok) {
+        rc = LYAF_EDEVICE;
+        break;
+      }
+      std::sort(t, t + kTuneReps);
+      const Candidate c{v, ps, t[kTuneReps / 2]};
       p->timings.push_back(c);
+      Candidate &best = ps ? best_pers : best_grid;
       if (c.us < best.us) best = c;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  destroy();
+  if (rc != LYAF_OK) return rc;
+  Candidate best = best_grid;
+  if (best_pers.variant >= 0 &&
+      (best.variant < 0 || best_pers.us < (1.0 - kTuneMargin) * best.us))
+    best = best_pers;
   if (best.variant < 0) return LYAF_EDEVICE;
   p->variant = best.variant;
   p->persistent_grid = best.persistent ? tau_persistent_grid(best.variant) : 0;

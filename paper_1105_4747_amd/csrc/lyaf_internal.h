@@ -68,17 +68,12 @@ struct Workspace {
   double *partials = nullptr;       // [kPartialsDoubles]
   NormState *norm = nullptr;        // [kNormPasses + 2]
   double *ratio = nullptr;          // backward-normalise scalar
-  // growable buffers
+  // growable buffers (the work lists of the entry points live in the API's
+  // per-(workspace, tile) records; a plan keeps its offsets here)
   SkewerConst *skc = nullptr;  int64_t skc_cap = 0;
   int64_t *offsets = nullptr;  int64_t off_cap = 0;
-  int2 *items = nullptr;       int64_t items_cap = 0;
-  int64_t *item_base = nullptr; int64_t ib_cap = 0;    // [S+1] first item of each skewer
   double *gpart = nullptr;     int64_t gpart_cap = 0;  // adjoint per-item FP64 partials
   unsigned int *queue = nullptr;                      // persistent work-queue counter
-  // instrument model: device offsets and work list (host mirror in the API)
-  int64_t *ins_off = nullptr;  int64_t ins_off_cap = 0;
-  int64_t *ins_oo = nullptr;   int64_t ins_oo_cap = 0;
-  int2 *ins_items = nullptr;   int64_t ins_items_cap = 0;
   // flux statistics: PDF partial counts, power-spectrum offsets (host mirror in the API)
   uint32_t *pdf_part = nullptr; int64_t pdf_part_cap = 0;
   int64_t *ps_off = nullptr;   int64_t ps_off_cap = 0;

@@ -42,7 +42,7 @@ EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_ba
             "lyaf_plan_create", "lyaf_plan_execute", "lyaf_plan_status", "lyaf_plan_describe",
             "lyaf_plan_destroy", "lyaf_instrument", "lyaf_instrument_backward",
             "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms", "lyaf_flux_pdf",
-            "lyaf_flux_power")
+            "lyaf_flux_power", "lyaf_kernel_timing", "lyaf_kernel_timing_read")
 
 
 class InstrumentParams(ctypes.Structure):
@@ -88,6 +88,11 @@ def load():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with paper_1105_4747_amd/build.py "
                 "(hipcc, gfx950); there is no CPU fallback")
+        from . import build as _build
+        if _build.built_hash(LIB_PATH) != _build.source_hash():
+            raise RuntimeError(
+                f"{LIB_PATH} was not built from the current sources (csrc/*.hip, *.h, "
+                "include/lyaf.h): rebuild it with paper_1105_4747_amd/build.py")
         lib = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
         PS, PP = ctypes.POINTER(Skewers), ctypes.POINTER(Params)
@@ -130,6 +135,10 @@ def load():
         lib.lyaf_flux_pdf.restype = i32
         lib.lyaf_flux_power.argtypes = [i64, pi64, vp, vp, dbl, vp, vp]
         lib.lyaf_flux_power.restype = i32
+        lib.lyaf_kernel_timing.argtypes = [i32]
+        lib.lyaf_kernel_timing.restype = i32
+        lib.lyaf_kernel_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), pi64]
+        lib.lyaf_kernel_timing_read.restype = i32
         _lib = lib
         return lib
 
@@ -293,6 +302,22 @@ def status_read(stream=None) -> int:
 
 def version() -> int:
     return int(load().lyaf_version())
+
+
+def kernel_timing(enable: bool) -> None:
+    """lyaf_kernel_timing: start (clearing earlier records) or stop recording
+    HIP events around the library's kernel launches."""
+    _check(load().lyaf_kernel_timing(1 if enable else 0), "lyaf_kernel_timing")
+
+
+def kernel_timing_read(name: str):
+    """lyaf_kernel_timing_read: (total ms, launches) recorded under ``name``
+    since the last read of it; waits for those launches."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(load().lyaf_kernel_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)),
+           "lyaf_kernel_timing_read")
+    return float(ms.value), int(n.value)
 
 
 class Plan:

@@ -237,3 +237,13 @@ def test_flux_power_null_pointers_and_empty(lib):
     assert f(1, off.ctypes.data_as(pi64), p, p, 0.8, None, None) == L.LYAF_EINVAL
     assert f(1, None, p, p, 0.8, p, None) == L.LYAF_EINVAL
     assert f(0, None, None, None, 0.8, None, None) == L.LYAF_OK
+
+
+def test_kernel_timing_records_nothing_when_idle(lib):
+    """Kernel timing is host bookkeeping until a launch is recorded: turning it
+    on and off and reading a name with no records makes no device call."""
+    assert lib.lyaf_kernel_timing_read(None, None, None) == L.LYAF_EINVAL
+    L.kernel_timing(True)
+    assert L.kernel_timing_read("tau") == (0.0, 0)
+    L.kernel_timing(False)
+    assert L.kernel_timing_read("tau") == (0.0, 0)

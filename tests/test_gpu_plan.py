@@ -114,6 +114,58 @@ def test_autotune_times_every_candidate_and_caches(tmp_path, monkeypatch):
     p2.close()
 
 
+def test_tune_cache_rejects_entries_of_another_device_or_shape(tmp_path, monkeypatch):
+    """A cached choice is reused only under its exact key (device name,
+    compute-unit count, batch-shape buckets, window): entries written for
+    another device, for another batch shape, or naming a shape the library
+    does not have are ignored, and the plan tunes afresh."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LYAF_TUNE_CACHE", str(cache))
+    w = ragged_mix(seed=47)
+    d = OnDevice(w)
+    p, *_ = _plan(w, d, autotune=True)
+    key = p.describe()["key"]
+    p.close()
+    fields_ = key.split("|")
+    assert fields_[0] == "v3" and fields_[1].startswith("gfx")
+    other_dev = "|".join([fields_[0], "gfx000", *fields_[2:]])
+    other_cus = "|".join([fields_[0], fields_[1], "cu1", *fields_[3:]])
+    other_shape = "|".join([*fields_[:3], "S2^30", *fields_[4:]])
+    cache.write_text(f"{other_dev} 1 0 1.0\n{other_cus} 1 0 1.0\n{other_shape} 1 0 1.0\n"
+                     f"{key} {L.NUM_SHAPES} 0 1.0\n{key} -1 0 1.0\n{key} 0 2 1.0\n")
+    p2, ts, F, A = _plan(w, d, autotune=True)
+    info = p2.describe()
+    print(f"case: stale tune cache {info}", flush=True)
+    assert info["key"] == key and not info["from_cache"], "a stale or malformed entry was used"
+    assert len(info["timings_us"]) == 2 * L.NUM_SHAPES
+    assert_tau_close(ts.cpu().numpy() / float(A.cpu()), oracle_tau(w), "re-tuned raw tau")
+    p2.close()
+    # the re-tuned entry was appended under the exact key and is used next time
+    assert cache.read_text().strip().split("\n")[-1].startswith(key + " ")
+    p3, *_ = _plan(w, d, autotune=True)
+    assert p3.describe()["from_cache"]
+    p3.close()
+
+
+def test_tuner_choice_follows_its_timings(tmp_path, monkeypatch):
+    """The tuner keeps the fastest one-workgroup-per-item launch unless the
+    persistent launch is faster by more than 2 %; every candidate is the
+    median of 11 replays."""
+    monkeypatch.setenv("LYAF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = ragged_mix(seed=49)
+    p, *_ = _plan(w, OnDevice(w), autotune=True)
+    info = p.describe()
+    p.close()
+    t = info["timings_us"]
+    grid = min((c for c in t if not c["persistent"]), key=lambda c: c["us"])
+    pers = min((c for c in t if c["persistent"]), key=lambda c: c["us"])
+    want = pers if pers["us"] < 0.98 * grid["us"] else grid
+    print(f"case: tuner choice grid={grid} persistent={pers} chose shape {info['shape']} "
+          f"persistent_grid {info['persistent_grid']}", flush=True)
+    assert info["shape"] == want["variant"]
+    assert (info["persistent_grid"] > 0) == bool(want["persistent"])
+
+
 @pytest.mark.slow
 def test_config3_plan_sampled():
     """20,000 ragged skewers through one tuned plan (persistent launch in a
