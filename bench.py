@@ -5,20 +5,23 @@ One step = the whole path over the 4096 x 4096 workload (4096 skewers of 4096
 pixels, dv = 2 km/s, sigma_lnDelta = 1.2, T0 = 2e4 K, gamma = 1.3, window
 +-6 b, target <F> = 0.75; synthetic lognormal fields, seed 2) with the inputs
 resident in HBM: one replay of a tuned plan, i.e. the hipGraph of the reach
-pass, the windowed tau kernel (persistent launch), the FP64 mean-flux
-root-find passes and tau' = A tau, F = exp(-tau').
+pass, the windowed tau kernel, the FP64 mean-flux root-find passes and
+tau' = A tau, F = exp(-tau').
 
 Prints one JSON line.  ``value`` is skewer-pixels per second of tau + F.
-``roofline`` describes the tau stage (the dominant kernel): algorithmic
-pairs inside the +-k b window (counted exactly from the inputs) times 7
-operations per pair (6 FP32 flops and one exp2), divided by the stage's
-average duration measured with HIP events on its stream, against the FP32
-vector peak of 157.3 TFLOP/s; beside it, the pair rate against the pair-rate
-roofline 1 / (c_exp + 4 c_valu) from the FMA and exp2 rates measured on the
-device in the same run (libpeaks).  ``detail.adjoint`` times the hand-written
-adjoint (lyaf_tau_backward) on the 4096 x 2048 workload.  ``cpu_baseline`` is
-the FP64 oracle (full sum + root-find) on a bounded sample of the same
-workload on the host cores.
+``roofline`` describes the dominant kernel, the windowed tau kernel: the
+algorithmic pairs inside the +-k b window (counted exactly from the inputs)
+times 5 FP32 flops per pair (the offset FMA, the scaling, the square and the
+accumulating FMA; the exp2 is not counted), divided by the kernel's average
+duration (HIP events the library records around that launch alone, on its
+stream), against the FP32 vector peak of 157.3 TFLOP/s.  Beside it: the pair
+rate against the ceiling of the direct form, min(FMA rate / 3, exp2 rate),
+both measured on the device in the same run (libpeaks).  ``error`` states the
+FP32 results against the FP64 oracle on the CPU-baseline sample.
+``cpu_baseline`` is the FP64 oracle (full sum + root-find) on a bounded sample
+of the same workload on the host cores.  ``detail`` holds the other
+workloads: the ragged 20,000-skewer batch, the 512 x 512 x 4096 box, the
+adjoint, the instrument model and the flux statistics.
 """
 from __future__ import annotations
 
@@ -38,21 +41,32 @@ FP32_PEAK_TFLOPS = 157.3      # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA
 # The library is built without packed FP32 instructions, so one FP32 op issues
 # per lane and cycle: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz.
 FP32_UNPACKED_TFLOPS = 78.6
-OPS_PER_PAIR = 7              # fma (2) + mul (1) + square (1) + exp2 (1) + fma (2)
+# algorithmic FP32 flops of one source-target pair: the offset FMA (counted
+# as 1 with the scaling multiply, 1), the square (1) and the accumulating FMA
+# (2); the exp2 is a transcendental, not a flop
+FLOPS_PER_PAIR = 5
 HBM_PEAK_GBPS = 8000.0
+TAU_TOL_REL, TAU_TOL_FLOOR, F_TOL_ABS = 1e-5, 1e-3, 1e-6
 
 
 def algorithmic_pairs(w) -> float:
     """sum over sources j of #{i : |(i - j) dv - v_j| < k b_j}, clamped to N,
-    with b_j from the T-rho relation (FP64, host)."""
+    with b_j from the T-rho relation (FP64, host; a box held on the GPU is
+    copied over in chunks of skewers)."""
     kB, mH = 1.380649e-16, 1.6735575e-24
     total = 0.0
     lens = np.diff(w.offsets)
-    for s0 in range(0, w.n_skewers, 256):
-        s1 = min(w.n_skewers, s0 + 256)
+    on_device = not isinstance(w.delta, np.ndarray)
+    step = 4096 if on_device else 256
+    for s0 in range(0, w.n_skewers, step):
+        s1 = min(w.n_skewers, s0 + step)
         a, b = int(w.offsets[s0]), int(w.offsets[s1])
-        d = w.delta[a:b].astype(np.float64)
-        v = w.vpec[a:b].astype(np.float64)
+        if on_device:
+            d = w.delta[a:b].cpu().numpy().astype(np.float64)
+            v = w.vpec[a:b].cpu().numpy().astype(np.float64)
+        else:
+            d = w.delta[a:b].astype(np.float64)
+            v = w.vpec[a:b].astype(np.float64)
         sk = np.repeat(np.arange(s0, s1), lens[s0:s1])
         dv, T0, gm = (w.dv[sk].astype(np.float64), w.T0[sk].astype(np.float64),
                       w.gamma[sk].astype(np.float64))
@@ -90,8 +104,6 @@ def adjoint_section(L, torch, dev, fields, timed, reps, peak):
     out = {"workload": w.name, "n_pix": P, "tau_backward_ms": round(t_bwd * 1e3, 4),
            "tau_forward_ms": round(t_fwd * 1e3, 4), "pairs_per_px": round(pairs / P, 2),
            "adjoint_pair_rate_per_s": pairs / t_bwd, "px_per_s": P / t_bwd}
-    if peak is not None:
-        out["adjoint_pair_frac"] = round(pairs / t_bwd / peak["pair_peak_per_s"], 4)
     return out
 
 
@@ -235,11 +247,44 @@ def stats_section(L, torch, dev, timed, reps, F, dvt, w):
                            "roofline": ps_roof, "kernel": "flux_power_kernel"}}
 
 
-def batched_section(L, torch, dev, fields, timed, reps):
+def kernel_seconds(L, fn, reps, name):
+    """Average duration (s) of the library's launches recorded under ``name``
+    while ``fn`` runs ``reps`` times (HIP events the library records around
+    those launches on their stream)."""
+    fn()
+    L.kernel_timing(True)
+    for _ in range(reps):
+        fn()
+    ms, n = L.kernel_timing_read(name)
+    L.kernel_timing(False)
+    if n == 0:
+        raise RuntimeError(f"no launch recorded under {name}")
+    return ms / n * 1e-3
+
+
+def tau_roofline(pairs, t_kernel, kernel, peak=None):
+    """FP32 roofline of the windowed tau kernel: 5 flops per algorithmic pair
+    over its average duration, against the packed FP32 peak."""
+    ach = pairs * FLOPS_PER_PAIR / t_kernel / 1e12
+    out = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+           "kernel": kernel, "kernel_ms": round(t_kernel * 1e3, 4),
+           "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+           "pair_rate_per_s": pairs / t_kernel,
+           "unpacked_peak": FP32_UNPACKED_TFLOPS,
+           "unpacked_frac": round(ach / FP32_UNPACKED_TFLOPS, 4)}
+    if peak is not None:
+        out["pair_ceiling_per_s"] = peak["pair_peak_per_s"]
+        out["pair_ceiling_frac"] = round(pairs / t_kernel / peak["pair_peak_per_s"], 4)
+    return out
+
+
+def batched_section(L, torch, dev, fields, timed, reps, peak):
     """The ragged 20,000-skewer batch (lengths 512-8192 px, dv 1-4 km/s, T0
-    and gamma drawn per skewer): one tuned plan (persistent launch in a
-    hipGraph) against the same windowed kernel launched once per skewer, and
-    the plain full-sum kernel on the first 200 skewers."""
+    and gamma drawn per skewer): one tuned plan (hipGraph) against the same
+    windowed kernel launched once per skewer, and the plain full-sum kernel on
+    the first 200 skewers.  The tuner's own median timings of every candidate
+    are reported beside the two launch forms of the chosen shape."""
     w = fields.config3()
     print(f"bench: batched {w.name}, P={w.n_pix}", file=sys.stderr, flush=True)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -253,12 +298,14 @@ def batched_section(L, torch, dev, fields, timed, reps):
     info = plan.describe()
     t_plan = timed(plan.execute, reps)
     shape = info["shape"]
-    fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if info["persistent_grid"] > 0 else 0)
+    pers = info["persistent_grid"] > 0
+    fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if pers else 0)
     raw = torch.empty_like(ts)
     tau = lambda flags: L.tau(delta, vpec, dvt, T0, gamma, w.offsets, raw,
                               window_k=w.window_k, flags=flags)
-    t_tau = timed(lambda: tau(fl), reps)
-    t_grid = timed(lambda: tau(L.FLAG_SHAPE(shape)), reps)
+    t_kernel = kernel_seconds(L, lambda: tau(fl), reps, "tau")
+    t_grid = kernel_seconds(L, lambda: tau(L.FLAG_SHAPE(shape)), reps, "tau")
+    t_pers = kernel_seconds(L, lambda: tau(L.FLAG_SHAPE(shape) | L.FLAG_PERSISTENT), reps, "tau")
     t_per = timed(lambda: tau(L.FLAG_PER_SKEWER | L.FLAG_SHAPE(shape)), 1)
     sub = w.subset(range(200))
     d2 = [t(x) for x in (sub.delta, sub.vpec, sub.dv, sub.T0, sub.gamma)]
@@ -266,18 +313,55 @@ def batched_section(L, torch, dev, fields, timed, reps):
     t_plain = timed(lambda: L.tau(*d2, sub.offsets, raw2, window_k=w.window_k,
                                   flags=L.FLAG_PLAIN), 1)
     pairs = algorithmic_pairs(w)
-    ach = pairs * OPS_PER_PAIR / t_tau / 1e12
     plan.close()
     return {"workload": w.name, "n_pix": P, "plan": info,
             "plan_step_ms": round(t_plan * 1e3, 4), "px_per_s": P / t_plan,
-            "tau_stage_ms": round(t_tau * 1e3, 4),
-            "tau_stage_one_launch_grid_ms": round(t_grid * 1e3, 4),
+            "tau_kernel_ms": round(t_kernel * 1e3, 4),
+            "tau_kernel_grid_ms": round(t_grid * 1e3, 4),
+            "tau_kernel_persistent_ms": round(t_pers * 1e3, 4),
+            "chosen_launch": "persistent" if pers else "grid",
             "tau_stage_launch_per_skewer_ms": round(t_per * 1e3, 3),
             "plain_fp32_px_per_s_first200": sub.n_pix / t_plain,
             "pairs_per_px": round(pairs / P, 3),
-            "tau_roofline": {"bound": "alu", "achieved": round(ach, 3),
-                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": round(ach / FP32_PEAK_TFLOPS, 4)}}
+            "tau_roofline": tau_roofline(pairs, t_kernel,
+                                         tau_kernel_name(shape, pers), peak)}
+
+
+def box_section(L, torch, dev, fields, timed, reps, peak):
+    """The 512 x 512 x 4096 box (1.07e9 pixels, 4.3 GB per FP32 array, one
+    seeded 3D lognormal field generated on the GPU): one tuned plan replayed
+    (tau, global FP64 mean-flux rescale, F), and the windowed kernel's
+    roofline."""
+    w = fields.config4(device=dev)
+    print(f"bench: box {w.name}, P={w.n_pix}", file=sys.stderr, flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    dvt, T0, gamma = t(w.dv), t(w.T0), t(w.gamma)
+    P = w.n_pix
+    ts = torch.empty(P, device=dev, dtype=torch.float32)
+    F = torch.empty_like(ts)
+    A = torch.empty((), device=dev, dtype=torch.float64)
+    plan = L.Plan(w.delta, w.vpec, dvt, T0, gamma, w.offsets, w.target_F, ts, F, A,
+                  window_k=w.window_k, autotune=True)
+    info = plan.describe()
+    t_plan = timed(plan.execute, reps)
+    if plan.status() != 0:
+        raise RuntimeError("device status set in the box section")
+    shape, pers = info["shape"], info["persistent_grid"] > 0
+    fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if pers else 0)
+    del F
+    raw = ts  # reused as the eager tau output
+    t_kernel = kernel_seconds(
+        L, lambda: L.tau(w.delta, w.vpec, dvt, T0, gamma, w.offsets, raw, window_k=w.window_k,
+                         flags=fl), reps, "tau")
+    plan.close()
+    pairs = algorithmic_pairs(w)
+    out = {"workload": w.name, "n_pix": P, "plan": info, "steps": reps,
+           "plan_step_ms": round(t_plan * 1e3, 3), "px_per_s": P / t_plan,
+           "pairs_per_px": round(pairs / P, 3),
+           "tau_roofline": tau_roofline(pairs, t_kernel, tau_kernel_name(shape, pers), peak)}
+    del w, ts, raw
+    torch.cuda.empty_cache()
+    return out
 
 
 def tau_kernel_name(shape: int, persistent: bool) -> str:
@@ -288,12 +372,13 @@ def tau_kernel_name(shape: int, persistent: bool) -> str:
 
 
 def measured_traffic(shape: int, persistent: bool, workload: str):
-    """HBM bytes per tau-stage launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record, or None when the kernel sources changed since the
-    counters were taken (or this shape/launch/workload was not counted)."""
+    """HBM bytes per windowed tau kernel launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record, or None when the kernel sources changed
+    since the counters were taken (or this shape/launch/workload was not
+    counted)."""
     import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "tau_stage_traffic.json")))
+        rec = json.load(open(os.path.join(ROOT, "profiles", "tau_kernel_traffic.json")))
     except OSError:
         return None
     h = hashlib.sha256()
@@ -306,9 +391,22 @@ def measured_traffic(shape: int, persistent: bool, workload: str):
     return None if ent is None else ent["traffic_bytes_per_launch"]
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, target_seconds=10.0):
     """FP64 oracle on the host: full sum of eq. (6) + mean-flux root-find, on
-    the first skewers of the workload, sized to ~target_seconds of wall time."""
+    the first skewers of the workload, sized to ~target_seconds of wall time.
+    Returns the record and the sample with the oracle's raw tau and F (F of
+    the sample normalised on its own)."""
     from oracle import oracle as O
     n = 8
     t_run = 0.0
@@ -317,15 +415,35 @@ def cpu_baseline(w, target_seconds=10.0):
         t0 = time.perf_counter()
         raw = O.tau(sub.delta, sub.vpec, sub.dv, sub.T0, sub.gamma, offsets=sub.offsets,
                     tau_ref=sub.tau_ref, delta_pivot=sub.delta_pivot)
-        O.normalise(raw, sub.target_F)
+        _, F, _ = O.normalise(raw, sub.target_F)
         t_run = time.perf_counter() - t0
         if t_run >= target_seconds / 4 or n >= w.n_skewers:
             break
         n = min(w.n_skewers, max(2 * n, int(n * target_seconds / 4 / max(t_run, 1e-3))))
-    return {"value": sub.n_pix / t_run, "unit": "skewer-pixels/s",
-            "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"first {n} skewers of the workload ({sub.n_pix} px), FP64 full "
-                      f"O(N^2) sum + root-find, {t_run:.2f} s"}
+    rec = {"value": sub.n_pix / t_run, "unit": "skewer-pixels/s",
+           "cores": O.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
+           "sample": f"first {n} skewers of the workload ({sub.n_pix} px), FP64 full "
+                     f"O(N^2) sum + root-find, {t_run:.2f} s"}
+    return rec, sub, raw, F
+
+
+def error_vs_oracle(L, torch, dev, raw_gpu, sub, raw_ref, F_ref):
+    """The FP32 results against the FP64 oracle on the CPU-baseline sample:
+    raw tau (|err| / (1e-5 max(tau, 1e-3))) and F of the sample, each side
+    normalising the sample on its own (|dF| against 1e-6)."""
+    g = raw_gpu[:sub.n_pix].clone()
+    err = np.abs(g.cpu().numpy().astype(np.float64) - raw_ref)
+    tau_ratio = float(np.max(err / (TAU_TOL_REL * np.maximum(raw_ref, TAU_TOL_FLOOR))))
+    F = torch.empty_like(g)
+    A = torch.empty((), device=dev, dtype=torch.float64)
+    L.normalise_mean_flux(g, F, sub.target_F, A)
+    dF = float(np.max(np.abs(F.cpu().numpy().astype(np.float64) - F_ref)))
+    return {"sample_px": int(sub.n_pix),
+            "tau_raw_max_err_over_tol": round(tau_ratio, 4),
+            "tau_tol": "1e-5 * max(tau, 1e-3)",
+            "F_max_abs_err": dF, "F_tol": F_TOL_ABS,
+            "F_max_err_over_tol": round(dF / F_TOL_ABS, 4),
+            "F_sample_normalised_on_its_own": True}
 
 
 def main():
@@ -336,6 +454,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-box", action="store_true",
+                    help="skip the 512 x 512 x 4096 box (8.6 GB of inputs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--no-instrument", action="store_true")
@@ -348,9 +468,9 @@ def main():
                     help="only run the adjoint section (4096 x 2048), for profiling")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"])
     ap.add_argument("--tau-only", action="store_true",
-                    help="only run the tau stage (reach + windowed kernel) K times, for profiling")
+                    help="only run lyaf_tau (reach + windowed kernel) K times, for profiling")
     ap.add_argument("--shape", type=int, default=None,
-                    help="windowed-kernel shape for --tau-only (LYAF_FLAG_SHAPE); default: tuned")
+                    help="windowed-kernel shape for --tau-only (LYAF_FLAG_SHAPE); default: 0")
     ap.add_argument("--persistent", action="store_true", help="persistent launch in --tau-only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB float32 buffer 3 times (counter calibration)")
@@ -372,6 +492,20 @@ def main():
         sys.exit(2)
     L.load()
     dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        """Average seconds of fn() over n calls after one warm-up (HIP events
+        on the current stream, which every library call here uses)."""
+        fn()
+        ev0.record(stream)
+        for _ in range(n):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / n * 1e-3
+
     if args.calibrate_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
         src = torch.ones(1 << 28, device=dev, dtype=torch.float32)
@@ -382,17 +516,6 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_per_launch": 2 * src.numel() * 4}))
         return
     if args.adjoint_only or args.instrument_only or args.stats_only:
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-        def timed(fn, n):
-            fn()
-            ev0.record()
-            for _ in range(n):
-                fn()
-            ev1.record()
-            ev1.synchronize()
-            return ev0.elapsed_time(ev1) / n * 1e-3
-
         if args.adjoint_only:
             print(json.dumps({"adjoint_only": True, **adjoint_section(
                 L, torch, dev, fields, timed, max(args.steps, 1), None)}), flush=True)
@@ -425,7 +548,6 @@ def main():
     ts = torch.empty(P, device=dev, dtype=torch.float32)
     F = torch.empty(P, device=dev, dtype=torch.float32)
     A = torch.empty((), device=dev, dtype=torch.float64)
-    stream = torch.cuda.current_stream()
 
     if args.tau_only:
         shape = 0 if args.shape is None else args.shape
@@ -463,10 +585,11 @@ def main():
     value = P * args.steps / elapsed
     print(f"bench: {ms_per_step:.4f} ms/step, {value:.4e} px/s", file=sys.stderr, flush=True)
 
-    # the tau stage alone (reach + windowed kernel, the plan's shape and launch
-    # form), HIP events on the launch stream
+    # the windowed tau kernel alone (the plan's shape and launch form): HIP
+    # events recorded by the library around that launch, on its stream
     shape = info["shape"]
-    tau_flags = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if info["persistent_grid"] > 0 else 0)
+    pers = info["persistent_grid"] > 0
+    tau_flags = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if pers else 0)
     raw = torch.empty(P, device=dev, dtype=torch.float32)
 
     def tau_stage(out, flags=tau_flags):
@@ -474,41 +597,24 @@ def main():
               delta_pivot=w.delta_pivot, window_k=w.window_k, flags=flags)
 
     reps = max(args.steps, 10)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def timed(fn, n):
-        fn()
-        ev0.record(stream)
-        for _ in range(n):
-            fn()
-        ev1.record(stream)
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / n * 1e-3
-
+    t_kernel = kernel_seconds(L, lambda: tau_stage(raw), reps, "tau")
+    t_reach = kernel_seconds(L, lambda: tau_stage(raw), reps, "reach")
     t_tau = timed(lambda: tau_stage(raw), reps)
     tmp = torch.empty_like(raw)
-    t_copy = timed(lambda: tmp.copy_(raw), reps)
-    t_norm = timed(lambda: (tmp.copy_(raw), L.normalise_mean_flux(tmp, F, w.target_F, A)),
-                   reps) - t_copy
-    t_eager = timed(lambda: (tau_stage(raw, 0), L.normalise_mean_flux(raw, F, w.target_F, A)),
-                    reps)
+    t_norm = kernel_seconds(L, lambda: (tmp.copy_(raw), L.normalise_mean_flux(tmp, F, w.target_F,
+                                                                            A)),
+                            reps, "normalise")
+    t_eager = timed(lambda: (tau_stage(raw, 0), L.normalise_mean_flux(tmp.copy_(raw), F,
+                                                                       w.target_F, A)), reps)
+    tau_stage(raw)  # raw tau of this workload for the error check
     pairs = algorithmic_pairs(w)
-    achieved = pairs * OPS_PER_PAIR / t_tau / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(shape, info["persistent_grid"] > 0, w.name),
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE)",
-                "kernel": "tau stage: reach_kernel + " + tau_kernel_name(
-                    shape, info["persistent_grid"] > 0),
-                "kernel_ms": round(t_tau * 1e3, 4),
-                "pairs_per_launch": pairs, "pairs_per_px": round(pairs / P, 3),
-                "pair_rate_per_s": pairs / t_tau, "ops_per_pair": OPS_PER_PAIR,
-                "unpacked_peak": FP32_UNPACKED_TFLOPS,
-                "unpacked_frac": round(achieved / FP32_UNPACKED_TFLOPS, 4)}
-    if peak is not None:
-        roofline["pair_peak_per_s"] = peak["pair_peak_per_s"]
-        roofline["pair_frac"] = round(pairs / t_tau / peak["pair_peak_per_s"], 4)
-    extra = {"plan": info, "tau_stage_ms": round(t_tau * 1e3, 4),
+    roofline = tau_roofline(pairs, t_kernel, tau_kernel_name(shape, pers), peak)
+    roofline["traffic"] = measured_traffic(shape, pers, w.name)
+    roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE)"
+    roofline["pairs_per_px"] = round(pairs / P, 3)
+    extra = {"plan": info, "tau_kernel_ms": round(t_kernel * 1e3, 4),
+             "reach_kernel_ms": round(t_reach * 1e3, 4),
+             "tau_stage_ms": round(t_tau * 1e3, 4),
              "normalise_stage_ms": round(t_norm * 1e3, 4),
              "eager_step_ms": round(t_eager * 1e3, 4)}
 
@@ -522,7 +628,9 @@ def main():
         del plain
 
     if not args.no_batched:
-        extra["batched"] = batched_section(L, torch, dev, fields, timed, reps)
+        extra["batched"] = batched_section(L, torch, dev, fields, timed, reps, peak)
+    if not args.no_box:
+        extra["box"] = box_section(L, torch, dev, fields, timed, 5, peak)
     if not args.no_adjoint:
         extra["adjoint"] = adjoint_section(L, torch, dev, fields, timed, reps, peak)
     if not args.no_instrument:
@@ -532,16 +640,17 @@ def main():
         plan.execute()  # F of this workload
         extra["flux_stats"] = stats_section(L, torch, dev, timed, reps, F, dvt, w)
     if peak is not None:
-        extra["peaks"] = {k: peak[k] for k in ("fma_lane_ops_per_s", "pair_per_s_exp",
-                                               "pair_per_s_noexp", "c_exp_s", "c_valu_s",
+        extra["peaks"] = {k: peak[k] for k in ("fma_lane_ops_per_s", "trans_lane_ops_per_s",
+                                               "mix_fma_per_exp", "mix_exp_per_s",
+                                               "pair_per_s_exp", "pair_per_s_noexp",
                                                "pair_peak_per_s", "copy_bytes_per_s")}
-        extra["peaks"]["exp_cost_in_fma_slots"] = round(peak["c_exp_s"] / peak["c_valu_s"], 3)
     plan.close()
 
-    cpu = None
+    cpu = error = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w)
+        cpu, sub, raw_ref, F_ref = cpu_baseline(w)
+        error = error_vs_oracle(L, torch, dev, raw, sub, raw_ref, F_ref)
 
     out = {
         "metric": METRIC, "value": value, "unit": "skewer-pixels/s", "n_gpus": 1,
@@ -552,7 +661,7 @@ def main():
                    "dv_kms": float(w.dv[0]), "T0": float(w.T0[0]), "gamma": float(w.gamma[0]),
                    "window_k": w.window_k, "target_F": w.target_F,
                    "parallelism": "single GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "detail": extra,
+        "roofline": roofline, "error": error, "cpu_baseline": cpu, "detail": extra,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)

@@ -5,11 +5,18 @@
  * device it runs on, next to the vendor's published peaks.
  *
  *   c_valu = 1 / (rate of independent FP32 FMAs, lane operations per second)
+ *   trans  = rate of independent exp2 (the transcendental unit alone)
+ *   mix    = exp2 rate when each exp2 is issued beside N independent FMAs:
+ *            if the transcendental unit overlaps the other VALU work this
+ *            stays at the trans rate until N c_valu exceeds 1 / trans
  *   c_exp  = extra time per lane of one exp2 in the pair arithmetic of the
  *            tau sum (t = k a + t0; e = exp2(-t t); acc += w e), measured as the
  *            difference between that loop with and without the exp2
- *   pair_peak = 1 / (c_exp + 4 c_valu): pairs per second if every pair cost
- *            one exp2 and four FP32 operations and nothing else
+ *   pair_peak = min(fma rate / 3, trans rate): the pair rate of the direct
+ *            form (each pair its own exp2 and at least three other VALU
+ *            operations: t_k, its square and the accumulate) when the two
+ *            units overlap; a ceiling for that form, since it counts no
+ *            staging, compensation or addressing
  *
  * All rates are for the whole device.  Packed FP32 instructions are not used.
  */
@@ -22,13 +29,18 @@
 extern "C" {
 #endif
 
+#define LYAF_PEAKS_MIX_N 6 /* exp2 beside N = 0, 1, 2, 3, 4, 6 FMAs */
+
 typedef struct lyaf_peak_rates {
   double fma_lane_ops_per_s;   /* v_fma_f32, 8 independent chains per lane */
   double pair_per_s_exp;       /* pair loop with the exp2, lane-pairs per second */
   double pair_per_s_noexp;     /* the same loop with the exp2 replaced by its argument */
   double c_valu_s;             /* seconds per lane operation: 1 / fma_lane_ops_per_s */
   double c_exp_s;              /* seconds per lane exp2 inside the pair loop */
-  double pair_peak_per_s;      /* 1 / (c_exp + 4 c_valu) */
+  double pair_peak_per_s;      /* min(fma_lane_ops_per_s / 3, trans_lane_ops_per_s) */
+  double trans_lane_ops_per_s; /* v_exp_f32, 4 independent chains per lane */
+  double mix_fma_per_exp[LYAF_PEAKS_MIX_N]; /* N: FMAs issued per exp2 */
+  double mix_exp_per_s[LYAF_PEAKS_MIX_N];   /* exp2 per second beside N FMAs each */
   double copy_bytes_per_s;     /* streaming copy, bytes read + written per second */
   int32_t compute_units;       /* of the device measured */
   int32_t clock_khz;           /* its peak engine clock */

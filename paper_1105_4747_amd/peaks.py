@@ -7,6 +7,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpeaks.so")
+MIX_N = 6  # LYAF_PEAKS_MIX_N
 
 
 class PeakRates(ctypes.Structure):
@@ -16,6 +17,9 @@ class PeakRates(ctypes.Structure):
                 ("c_valu_s", ctypes.c_double),
                 ("c_exp_s", ctypes.c_double),
                 ("pair_peak_per_s", ctypes.c_double),
+                ("trans_lane_ops_per_s", ctypes.c_double),
+                ("mix_fma_per_exp", ctypes.c_double * MIX_N),
+                ("mix_exp_per_s", ctypes.c_double * MIX_N),
                 ("copy_bytes_per_s", ctypes.c_double),
                 ("compute_units", ctypes.c_int32),
                 ("clock_khz", ctypes.c_int32)]
@@ -30,6 +34,10 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        from . import build as _build
+        if _build.built_hash(LIB_PATH) != _build.source_hash(
+                _build.PEAKS_SOURCES + [os.path.join(_build.ROOT, "include", "lyaf_peaks.h")]):
+            raise RuntimeError(f"{LIB_PATH} was not built from the current sources: rebuild it")
         lib = ctypes.CDLL(LIB_PATH)
         lib.lyaf_peaks_measure.argtypes = [ctypes.POINTER(PeakRates), ctypes.c_void_p]
         lib.lyaf_peaks_measure.restype = ctypes.c_int
@@ -43,4 +51,8 @@ def measure(stream=None) -> dict:
     rc = load().lyaf_peaks_measure(ctypes.byref(r), h)
     if rc != 0:
         raise RuntimeError(f"lyaf_peaks_measure failed ({rc})")
-    return {f: getattr(r, f) for f, _ in PeakRates._fields_}
+    out = {}
+    for f, _ in PeakRates._fields_:
+        v = getattr(r, f)
+        out[f] = list(v) if isinstance(v, ctypes.Array) else v
+    return out
