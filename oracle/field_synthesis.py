@@ -96,3 +96,37 @@ def explicit_sum(F, x, y, z):
                 ph = 2.0 * np.pi * (a * x + b * y + c * z) / N
                 tot += w * (F[a, b, c] * np.exp(1j * ph)).real
     return tot / N ** 3
+
+
+def skewer_fields_direct(modes, pk, dk, amp, L, k_F, E_plus, sx, sy, chunk=16):
+    """The same outputs as ``skewer_fields`` without forming the real grid:
+    for each sight-line, C(kz) = sum_{kx, ky} F(k) e^{2 pi i (kx x + ky y)/n}
+    directly, then the sum over kz by numpy's inverse real FFT along z (which
+    takes the real part of the kz = 0 and n/2 terms, as the header's sum does).
+    For grids too large for a full inverse transform."""
+    N = modes.shape[0]
+    kx, ky, kz = wavenumbers(N, L)
+    k2 = kx[:, None, None] ** 2 + ky[None, :, None] ** 2 + kz[None, None, :] ** 2
+    kmag = np.sqrt(k2)
+    A = amp * np.sqrt(power_at(kmag, pk, dk))
+    filt = 1.0 / (1.0 + k2 / (k_F * k_F)) if np.isfinite(k_F) else 1.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        vf = np.where(k2 > 0, E_plus * kz[None, None, :] / k2, 0.0)
+    del k2, kmag
+    g = np.asarray(modes, np.complex128)
+    Fb = A * filt * g
+    Fv = 1j * A * vf * g
+    del g, A, vf
+    n_idx = np.arange(N)
+    out_b = np.empty((len(sx), N))
+    out_v = np.empty((len(sx), N))
+    for s0 in range(0, len(sx), chunk):
+        xs = np.asarray(sx[s0:s0 + chunk])
+        ys = np.asarray(sy[s0:s0 + chunk])
+        ex = np.exp(2j * np.pi * np.outer(xs, n_idx) / N)  # [s, kx]
+        ey = np.exp(2j * np.pi * np.outer(ys, n_idx) / N)  # [s, ky]
+        Cb = np.einsum("sa,abc,sb->sc", ex, Fb, ey, optimize=True)
+        Cv = np.einsum("sa,abc,sb->sc", ex, Fv, ey, optimize=True)
+        out_b[s0:s0 + chunk] = np.fft.irfft(Cb, n=N, axis=1) / N ** 2
+        out_v[s0:s0 + chunk] = np.fft.irfft(Cv, n=N, axis=1) / N ** 2
+    return out_b, out_v
