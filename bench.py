@@ -247,6 +247,52 @@ def stats_section(L, torch, dev, timed, reps, F, dvt, w):
                            "roofline": ps_roof, "kernel": "flux_power_kernel"}}
 
 
+def _hbm_roof(nbytes, seconds):
+    gbs = nbytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def fields_section(L, torch, dev, fields, timed, reps):
+    """Skewer-only field synthesis (lyaf_field_skewers, eqs. 1 and 3, Appendix B)
+    on a 1024^3 grid with 6,250 sight-lines: the whole call and each of its
+    three kernels (HIP events the library records), each kernel against HBM
+    with its algorithmic bytes."""
+    w = fields.field_synthesis_workload(device=dev)
+    print(f"bench: {w.name}", file=sys.stderr, flush=True)
+    n, S = w.n, len(w.sx)
+    H = n // 2 + 1
+    pk = torch.from_numpy(w.pk).to(dev)
+    b = torch.empty((S, n), device=dev, dtype=torch.float32)
+    v = torch.empty_like(b)
+    call = lambda: L.field_skewers(w.modes, pk, w.sx, w.sy, b, v, n, w.box, w.amp, w.k_F,
+                                   w.E_plus, w.dk)
+    t_call = timed(call, reps)
+    t_ky = kernel_seconds(L, call, reps, "field_ky")
+    t_kx = kernel_seconds(L, call, reps, "field_kx")
+    t_z = kernel_seconds(L, call, reps, "field_z")
+    if L.status_read() != 0:
+        raise RuntimeError("device status set in the field-synthesis section")
+    rows = len(np.unique(w.sy))
+    modes = float(n) * n * H
+    groups = sum(-(-c // 8) for c in np.unique(w.sy, return_counts=True)[1])
+    ky_bytes = 8.0 * modes + 2 * 8.0 * rows * n * H          # modes in, both fields' rows out
+    kx_bytes = 2 * 8.0 * groups * n * H + 2 * 16.0 * S * H   # rows in (per group), sums out
+    z_bytes = 2 * 16.0 * S * H + 2 * 4.0 * S * n
+    kernels = {"field_ky_kernel": (t_ky, ky_bytes), "field_kx_kernel": (t_kx, kx_bytes),
+               "field_z_kernel": (t_z, z_bytes)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    return {"workload": w.name, "n": n, "sight_lines": S, "rows_in_use": rows,
+            "call_ms": round(t_call * 1e3, 4),
+            "sight_line_pixels_per_s": S * n / t_call, "modes_per_s": modes / t_call,
+            "kernels": {k: {"ms": round(t * 1e3, 4), "algorithmic_bytes": int(nb),
+                            "roofline": _hbm_roof(nb, t)} for k, (t, nb) in kernels.items()},
+            "call_minimum_bytes": int(8.0 * modes + 2 * 4.0 * S * n),
+            "call_minimum_frac": round(8.0 * modes / t_call / 1e9 / HBM_PEAK_GBS, 4),
+            "dominant_kernel": dom, "roofline": {**_hbm_roof(kernels[dom][1], kernels[dom][0]),
+                                                 "kernel": dom}}
+
+
 def kernel_seconds(L, fn, reps, name):
     """Average duration (s) of the library's launches recorded under ``name``
     while ``fn`` runs ``reps`` times (HIP events the library records around
@@ -460,6 +506,9 @@ def main():
     ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--no-instrument", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--no-fields", action="store_true")
+    ap.add_argument("--fields-only", action="store_true",
+                    help="only run the field-synthesis section, for profiling")
     ap.add_argument("--stats-only", action="store_true",
                     help="only run the flux-statistics section (PDF, power spectrum), for profiling")
     ap.add_argument("--instrument-only", action="store_true",
@@ -514,6 +563,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_per_launch": 2 * src.numel() * 4}))
+        return
+    if args.fields_only:
+        print(json.dumps({"fields_only": True, **fields_section(
+            L, torch, dev, fields, timed, max(args.steps, 1))}), flush=True)
         return
     if args.adjoint_only or args.instrument_only or args.stats_only:
         if args.adjoint_only:
@@ -636,6 +689,9 @@ def main():
     if not args.no_instrument:
         plan.execute()  # F of this workload
         extra["instrument"] = instrument_section(L, torch, dev, fields, timed, reps, F, dvt, w)
+    if not args.no_fields:
+        extra["field_synthesis"] = fields_section(L, torch, dev, fields, timed, reps)
+        torch.cuda.empty_cache()
     if not args.no_stats:
         plan.execute()  # F of this workload
         extra["flux_stats"] = stats_section(L, torch, dev, timed, reps, F, dvt, w)

@@ -244,6 +244,54 @@ int lyaf_flux_pdf(int64_t n_pix, const float *F, int64_t *counts, void *stream);
 int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, const float *F,
                     double mean_F, float *power, void *stream);
 
+/* ---- skewer-only field synthesis (Section 2.1, eqs. 1 and 3; Appendix B) ----
+ *
+ * The linear fields that feed the optical depths, generated in Fourier space
+ * and brought back to real space only along the sight-lines that are needed.
+ * A Gaussian field g(k) is given on the half-spectrum of a real n^3 grid of a
+ * periodic box of side L, k = (2 pi / L)(mx, my, mz) with mx, my signed
+ * (index i stands for i - n when i > n/2) and mz = 0 .. n/2:
+ *
+ *   delta_DM(k) = amp sqrt(P(|k|)) g(k),   P linearly interpolated from
+ *                 pk[j] at |k| = j dk, 0 past the table's last node;
+ *   delta_b(k)  = delta_DM(k) / (1 + k^2 / k_F^2)             (eq. 1)
+ *   v_z(k)      = E_plus i (k_z / k^2) delta_DM(k), 0 at k = 0  (eq. 3, the
+ *                 component along the sight-lines, which run along z);
+ *
+ * and on sight-line s, the column (sx[s], sy[s]), for z = 0 .. n-1,
+ *
+ *   f_s(z) = n^-3 sum_{mx, my} sum_{mz=0}^{n/2} c_mz Re[F(k) e^{2 pi i (mx x + my y + mz z)/n}]
+ *
+ * with c_mz = 1 at mz = 0 and n/2 and 2 otherwise (the real field whose
+ * half-spectrum is F, numpy's irfftn).  The transforms run across the
+ * (kx, ky) planes, keeping only the rows y that some sight-line uses, then
+ * along each sight-line: FP32 data and arithmetic for the my transform, FP64
+ * for the mx sums and the z transform, FP32 multipliers, float output.  The
+ * table should reach the largest |k| of the grid, sqrt(3) pi n / L (or end
+ * at zero power): a mode at the table's last node is decided in FP32. */
+typedef struct {
+  int64_t n;        /* grid points per side: a power of two, 4 .. 2048 */
+  double box;       /* side L of the periodic box (> 0, finite) */
+  double amp;       /* normalisation of delta_DM (finite) */
+  double k_F;       /* filtering wavenumber of eq. (1) (> 0; +INFINITY: no filter) */
+  double E_plus;    /* velocity factor of eq. (3) (finite) */
+  double dk;        /* spacing of the power table (> 0, finite) */
+  int64_t n_table;  /* entries of the power table (1 .. 2^31 - 1) */
+} lyaf_field_params;
+
+/* delta_b and v_z on n_lines sight-lines.
+ *   modes: DEVICE complex float [n][n][n/2+1] (interleaved re, im; mz fastest),
+ *          the half-spectrum g(k), read only.
+ *   pk:    DEVICE double [n_table], the power table.
+ *   sx, sy: HOST int32 [n_lines], columns in 0 .. n-1 (repeats allowed).
+ *   delta_b, v_z: DEVICE float [n_lines][n], written (sight-line s at s*n).
+ * The library keeps a workspace of 16 R n (n/2+1) + 32 n_lines (n/2+1) bytes,
+ * R the number of distinct sy values (about 8.6 GB at n = 1024 with every
+ * row in use).  Errors: EINVAL (host checks above), EDEVICE, ENOMEM. */
+int lyaf_field_skewers(const lyaf_field_params *fp, const void *modes, const double *pk,
+                       int64_t n_lines, const int32_t *sx, const int32_t *sy, float *delta_b,
+                       float *v_z, void *stream);
+
 /* ---- plans: the whole forward, tuned and captured once, replayed many times ----
  *
  * Section 2.3 applies the same steps to every spectrum of a survey: eq. (6) per
@@ -303,7 +351,8 @@ int lyaf_status_read(void *stream, uint32_t *device_status);
  *   "tau"        the windowed tau kernel of lyaf_tau (with the queue reset of a
  *                persistent launch); "tau_plain" the plain full-sum kernels
  *   "normalise", "normalise_backward", "tau_adjoint", "instrument",
- *   "instrument_backward", "flux_pdf", "flux_power".
+ *   "instrument_backward", "flux_pdf", "flux_power",
+ *   "field_ky", "field_kx", "field_z" (the three kernels of lyaf_field_skewers).
  * Launches under stream capture (plans, caller graphs) are not recorded, and
  * recording stops after 65536 launches.  lyaf_kernel_timing(0) stops and
  * clears.  lyaf_kernel_timing_read waits for the recorded launches of `name`,

@@ -30,6 +30,9 @@ with c_kz = 1 for kz = 0 and N/2 and 2 otherwise (the Hermitian partners of
 the modes with 0 < kz < N/2 are implied); numpy's irfftn computes exactly this.
 Outputs: delta_b and v_z on the S sight-lines, float64 [S, N] each.
 
+The plane-by-plane path (``skewer_fields_planes``) serves grids too large for
+the full inverse transform and is pinned against ``skewer_fields``.
+
 Parity status: pinned by the explicit sum above (brute force on small grids),
 single-mode closed forms for delta_b and v_z, Parseval's identity, the
 filter's limit k_F -> infinity, linear interpolation of a table that is linear
@@ -130,3 +133,33 @@ def skewer_fields_direct(modes, pk, dk, amp, L, k_F, E_plus, sx, sy, chunk=16):
         out_b[s0:s0 + chunk] = np.fft.irfft(Cb, n=N, axis=1) / N ** 2
         out_v[s0:s0 + chunk] = np.fft.irfft(Cv, n=N, axis=1) / N ** 2
     return out_b, out_v
+
+
+def skewer_fields_planes(modes, pk, dk, amp, L, k_F, E_plus, sx, sy):
+    """The same outputs as ``skewer_fields`` for a few sight-lines of a grid
+    too large to hold in FP64: one mx plane of the half-spectrum at a time,
+    its multipliers (eqs. 1 and 3) formed for that plane only, then
+    C_s(mz) += e^{2 pi i mx x_s / N} sum_my e^{2 pi i my y_s / N} F(mx, my, mz),
+    and the sum over mz by numpy's inverse real FFT along z (which keeps the
+    real part of the mz = 0 and N/2 terms, as the header's sum does).
+    ``modes`` may be complex64; each plane is widened to complex128."""
+    N = modes.shape[0]
+    kx, ky, kz = wavenumbers(N, L)
+    sx = np.asarray(sx, np.int64)
+    sy = np.asarray(sy, np.int64)
+    n_idx = np.arange(N)
+    ey = np.exp(2j * np.pi * np.outer(sy, n_idx) / N)  # [s, my]
+    Cb = np.zeros((len(sx), N // 2 + 1), np.complex128)
+    Cv = np.zeros_like(Cb)
+    ky2kz2 = ky[:, None] ** 2 + kz[None, :] ** 2
+    for a in range(N):
+        k2 = kx[a] ** 2 + ky2kz2
+        A = amp * np.sqrt(power_at(np.sqrt(k2), pk, dk))
+        filt = 1.0 / (1.0 + k2 / (k_F * k_F)) if np.isfinite(k_F) else 1.0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            vf = np.where(k2 > 0, E_plus * kz[None, :] / k2, 0.0)
+        g = np.asarray(modes[a], np.complex128)
+        ex = np.exp(2j * np.pi * a * sx / N)[:, None]  # [s, 1]
+        Cb += ex * (ey @ (A * filt * g))
+        Cv += ex * (ey @ (1j * A * vf * g))
+    return np.fft.irfft(Cb, n=N, axis=1) / N ** 2, np.fft.irfft(Cv, n=N, axis=1) / N ** 2

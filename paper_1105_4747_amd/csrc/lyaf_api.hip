@@ -366,6 +366,95 @@ int ensure_ps_plan(Workspace *ws, int64_t S, const int64_t *offsets, HostPsPlan 
   return LYAF_OK;
 }
 
+// The shared FFT twiddle table of a workspace, built on first use.
+int ensure_twiddles(Workspace *ws, hipStream_t st) {
+  if (ws->ps_twiddle) return LYAF_OK;
+  hipError_t e = hipMalloc((void **)&ws->ps_twiddle, sizeof(double2) * (kPsMaxN / 4));
+  if (e != hipSuccess) {
+    ws->ps_twiddle = nullptr;
+    return map_err(e);
+  }
+  return map_err(launch_twiddles(ws->ps_twiddle, st));
+}
+
+// Sight-line plan of the field synthesis: the rows y in use (ascending), the
+// sight-lines grouped by row (at most kFieldLinesPerGroup per group), with
+// device copies; rebuilt only when the grid side or the columns change.
+struct HostFieldPlan {
+  int64_t n = 0;
+  std::vector<int32_t> sx, sy;
+  int n_rows = 0, n_groups = 0;
+  int *h_rows = nullptr; int4 *h_groups = nullptr; int2 *h_lines = nullptr;
+  int *h_first = nullptr;
+  int64_t h_rows_cap = 0, h_groups_cap = 0, h_lines_cap = 0, h_first_cap = 0;
+  int *d_rows = nullptr; int4 *d_groups = nullptr; int2 *d_lines = nullptr;
+  int *d_first = nullptr;  // [rows + 1]: first line of each row
+  int64_t d_rows_cap = 0, d_groups_cap = 0, d_lines_cap = 0, d_first_cap = 0;
+};
+std::map<Workspace *, HostFieldPlan> g_field_plans;
+
+int ensure_field_plan(Workspace *ws, int64_t n, int64_t S, const int32_t *sx, const int32_t *sy,
+                      HostFieldPlan **out) {
+  HostFieldPlan &hp = g_field_plans[ws];
+  *out = &hp;
+  if (hp.n == n && (int64_t)hp.sx.size() == S &&
+      memcmp(hp.sx.data(), sx, sizeof(int32_t) * (size_t)S) == 0 &&
+      memcmp(hp.sy.data(), sy, sizeof(int32_t) * (size_t)S) == 0)
+    return LYAF_OK;
+  hipError_t e;
+  if ((e = hipStreamSynchronize(ws->stream)) != hipSuccess) return map_err(e);
+  hp.n = 0;
+  // sight-lines ordered by row, then by their index
+  std::vector<int32_t> order((size_t)S);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return sy[a] < sy[b]; });
+  std::vector<int> rows, first;
+  std::vector<int4> groups;
+  for (int64_t i = 0; i < S;) {
+    const int y = sy[order[(size_t)i]];
+    int64_t j = i;
+    while (j < S && sy[order[(size_t)j]] == y) ++j;
+    const int ri = (int)rows.size();
+    rows.push_back(y);
+    first.push_back((int)i);
+    for (int64_t g = i; g < j; g += kFieldLinesPerGroup)
+      groups.push_back(make_int4(ri, (int)g, (int)std::min<int64_t>(kFieldLinesPerGroup, j - g), 0));
+    i = j;
+  }
+  first.push_back((int)S);
+  const int64_t nr = (int64_t)rows.size(), ng = (int64_t)groups.size();
+  if ((e = grow_host(hp.h_first, hp.h_first_cap, nr + 1)) != hipSuccess ||
+      (e = grow_dev(hp.d_first, hp.d_first_cap, nr + 1)) != hipSuccess ||
+      (e = grow_host(hp.h_rows, hp.h_rows_cap, nr)) != hipSuccess ||
+      (e = grow_host(hp.h_groups, hp.h_groups_cap, ng)) != hipSuccess ||
+      (e = grow_host(hp.h_lines, hp.h_lines_cap, S)) != hipSuccess ||
+      (e = grow_dev(hp.d_rows, hp.d_rows_cap, nr)) != hipSuccess ||
+      (e = grow_dev(hp.d_groups, hp.d_groups_cap, ng)) != hipSuccess ||
+      (e = grow_dev(hp.d_lines, hp.d_lines_cap, S)) != hipSuccess)
+    return map_err(e);
+  std::copy(rows.begin(), rows.end(), hp.h_rows);
+  std::copy(first.begin(), first.end(), hp.h_first);
+  std::copy(groups.begin(), groups.end(), hp.h_groups);
+  for (int64_t i = 0; i < S; ++i)
+    hp.h_lines[i] = make_int2(order[(size_t)i], sx[order[(size_t)i]]);
+  if ((e = hipMemcpyAsync(hp.d_first, hp.h_first, sizeof(int) * (size_t)(nr + 1),
+                          hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
+      (nr > 0 && (e = hipMemcpyAsync(hp.d_rows, hp.h_rows, sizeof(int) * (size_t)nr,
+                                     hipMemcpyHostToDevice, ws->stream)) != hipSuccess) ||
+      (ng > 0 && (e = hipMemcpyAsync(hp.d_groups, hp.h_groups, sizeof(int4) * (size_t)ng,
+                                     hipMemcpyHostToDevice, ws->stream)) != hipSuccess) ||
+      (S > 0 && (e = hipMemcpyAsync(hp.d_lines, hp.h_lines, sizeof(int2) * (size_t)S,
+                                    hipMemcpyHostToDevice, ws->stream)) != hipSuccess))
+    return map_err(e);
+  hp.n_rows = (int)nr;
+  hp.n_groups = (int)ng;
+  hp.sx.assign(sx, sx + S);
+  hp.sy.assign(sy, sy + S);
+  hp.n = n;
+  return LYAF_OK;
+}
+
 InsArgs make_ins_args(Workspace *ws, const HostInsPlan *hp, const float *dv,
                       const lyaf_instrument_params *ip) {
   InsArgs a;
@@ -608,18 +697,72 @@ int lyaf_flux_power(int64_t n_skewers, const int64_t *offsets, const float *dv, 
   if (rc) return rc;
   HostPsPlan *hp = nullptr;
   if ((rc = ensure_ps_plan(ws, n_skewers, offsets, &hp))) return rc;
-  if (!ws->ps_twiddle) {
-    hipError_t e = hipMalloc((void **)&ws->ps_twiddle, sizeof(double2) * (kPsMaxN / 4));
-    if (e != hipSuccess) {
-      ws->ps_twiddle = nullptr;
-      return map_err(e);
-    }
-    if ((e = launch_twiddles(ws->ps_twiddle, st)) != hipSuccess) return map_err(e);
-  }
+  if ((rc = ensure_twiddles(ws, st))) return rc;
   return map_err(timed("flux_power", st, [&] {
     return launch_flux_power(n_skewers, hp->max_n, F, ws->ps_off, ws->ps_mo, dv,
                              1.0 / mean_F, ws->ps_twiddle, power, ws->status, st);
   }));
+}
+
+int lyaf_field_skewers(const lyaf_field_params *fp, const void *modes, const double *pk,
+                       int64_t n_lines, const int32_t *sx, const int32_t *sy, float *delta_b,
+                       float *v_z, void *stream) {
+  if (!fp || n_lines < 0) return LYAF_EINVAL;
+  const int64_t N = fp->n;
+  if (N < 4 || N > kFieldMaxN || (N & (N - 1)) != 0) return LYAF_EINVAL;
+  if (!(fp->box > 0.0) || !isfinite(fp->box) || !isfinite(fp->amp)) return LYAF_EINVAL;
+  if (!(fp->k_F > 0.0) || !isfinite(fp->E_plus)) return LYAF_EINVAL;  // k_F = +INF allowed
+  if (!(fp->dk > 0.0) || !isfinite(fp->dk)) return LYAF_EINVAL;
+  if (fp->n_table < 1 || fp->n_table > INT32_MAX) return LYAF_EINVAL;
+  if (n_lines == 0) return LYAF_OK;
+  if (n_lines > INT32_MAX || !modes || !pk || !sx || !sy || !delta_b || !v_z)
+    return LYAF_EINVAL;
+  for (int64_t s = 0; s < n_lines; ++s)
+    if (sx[s] < 0 || sx[s] >= N || sy[s] < 0 || sy[s] >= N) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace *ws = nullptr;
+  int rc = get_ws(st, &ws);
+  if (rc) return rc;
+  HostFieldPlan *hp = nullptr;
+  if ((rc = ensure_field_plan(ws, N, n_lines, sx, sy, &hp))) return rc;
+  if ((rc = ensure_twiddles(ws, st))) return rc;
+  const int64_t H = N / 2 + 1;
+  hipError_t e;
+  if ((e = field_kernel_attributes()) != hipSuccess ||
+      (e = grow_dev(ws->field_T, ws->field_T_cap, 2 * (int64_t)hp->n_rows * N * H)) !=
+          hipSuccess ||
+      (e = grow_dev(ws->field_C, ws->field_C_cap, 2 * n_lines * H)) != hipSuccess)
+    return map_err(e);
+  FieldArgs a;
+  a.modes = static_cast<const float2 *>(modes);
+  a.pk = pk;
+  a.N = (int)N;
+  a.H = (int)H;
+  a.n_table = (int)fp->n_table;
+  a.n_rows = hp->n_rows;
+  const double kfun = 2.0 * M_PI / fp->box;
+  a.kfun = (float)kfun;
+  a.inv_dk = (float)(1.0 / fp->dk);
+  a.amp = (float)fp->amp;
+  a.kfun2_inv_kF2 = isinf(fp->k_F) ? 0.f : (float)(kfun * kfun / (fp->k_F * fp->k_F));
+  a.E_over_kfun = (float)(fp->E_plus / kfun);
+  a.inv_n3 = 1.0 / ((double)N * (double)N * (double)N);
+  a.rows = hp->d_rows;
+  a.groups = hp->d_groups;
+  a.lines = hp->d_lines;
+  a.Tb = ws->field_T;
+  a.Tv = ws->field_T + (int64_t)hp->n_rows * N * H;
+  a.Cb = ws->field_C;
+  a.Cv = ws->field_C + n_lines * H;
+  a.delta_b = delta_b;
+  a.v_z = v_z;
+  a.twiddle = ws->ps_twiddle;
+  if ((e = timed("field_ky", st, [&] { return launch_field_ky(a, st); })) != hipSuccess ||
+      (e = timed("field_kx", st, [&] { return launch_field_kx(a, hp->n_groups, st); })) !=
+          hipSuccess)
+    return map_err(e);
+  return map_err(timed("field_z", st, [&] { return launch_field_z(a, (int)n_lines, st); }));
 }
 
 double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {

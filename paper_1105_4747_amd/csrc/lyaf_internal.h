@@ -79,6 +79,10 @@ struct Workspace {
   int64_t *ps_off = nullptr;   int64_t ps_off_cap = 0;
   int64_t *ps_mo = nullptr;    int64_t ps_mo_cap = 0;
   double2 *ps_twiddle = nullptr;                      // [kPsMaxN / 4], built once
+  // field synthesis: the intermediates of both fields (my-transformed rows,
+  // then the mx-transformed sight-lines)
+  float2 *field_T = nullptr;   int64_t field_T_cap = 0;
+  double2 *field_C = nullptr;  int64_t field_C_cap = 0;
 };
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
@@ -154,6 +158,33 @@ hipError_t launch_twiddles(double2 *T, hipStream_t st);  // kPsMaxN / 4 entries
 hipError_t launch_flux_power(int64_t n_skewers, int max_n, const float *F, const int64_t *offsets,
                              const int64_t *mode_off, const float *dv, double inv_mean,
                              const double2 *T, float *P, uint32_t *status, hipStream_t st);
+// Skewer-only field synthesis (eqs. 1 and 3, Appendix B).
+constexpr int kFieldMaxN = 2048;  // grid points per side
+struct FieldArgs {
+  const float2 *modes;   // device [N][N][N/2+1] Gaussian modes g(k)
+  const double *pk;      // device [n_table] power table, P at |k| = j dk
+  int N, H;              // grid side and N/2 + 1
+  int n_table, n_rows;   // table entries; rows y that some sight-line uses
+  float kfun;            // 2 pi / L
+  float inv_dk;          // 1 / dk
+  float amp;             // delta_DM = amp sqrt(P) g
+  float kfun2_inv_kF2;   // (2 pi / L)^2 / k_F^2 (0: no filter)
+  float E_over_kfun;     // E_+ / (2 pi / L)
+  double inv_n3;         // N^-3
+  const int *rows;       // device [n_rows]: y of each kept row
+  const int4 *groups;    // device [n_groups]: (row index, first line, count, 0)
+  const int2 *lines;     // device [S]: (sight-line, x), grouped by row
+  float2 *Tb, *Tv;       // device [n_rows][N][H] after the my transform
+  double2 *Cb, *Cv;      // device [S][H] after the mx transform
+  float *delta_b, *v_z;  // device [S][N] outputs
+  const double2 *twiddle;  // the shared FFT table (kFftTableLen / 2 entries)
+};
+int field_ky_columns(int N);  // mz values per field_ky work item
+hipError_t field_kernel_attributes();
+hipError_t launch_field_ky(const FieldArgs &a, hipStream_t st);
+hipError_t launch_field_kx(const FieldArgs &a, int n_groups, hipStream_t st);
+hipError_t launch_field_z(const FieldArgs &a, int n_lines, hipStream_t st);
+constexpr int kFieldLinesPerGroup = 8;
 hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
                               const int64_t *item_base_dev, const float *g,
                               float *gdelta, float *gvpec, double *gT0,

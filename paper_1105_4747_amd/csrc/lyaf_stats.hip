@@ -24,6 +24,7 @@
 // O_m = (Z_m - conj Z_{M-m}) / 2i.
 #include <algorithm>
 
+#include "lyaf_fft.h"
 #include "lyaf_internal.h"
 
 namespace lyaf {
@@ -81,93 +82,10 @@ __global__ __launch_bounds__(64) void flux_pdf_sum_kernel(const uint32_t *__rest
   if (threadIdx.x == 0) counts[slot] = (int64_t)s;
 }
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x));
-}
-__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// multiply by -i and by +i
-__device__ inline double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }
-__device__ inline double2 mul_pi(double2 a) { return make_double2(-a.y, a.x); }
-
-__device__ inline void dft4(double2 a0, double2 a1, double2 a2, double2 a3, double2 &y0,
-                            double2 &y1, double2 &y2, double2 &y3) {
-  const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
-  const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
-  y0 = cadd(s02, s13);
-  y1 = cadd(d02, mul_mi(d13));
-  y2 = csub(s02, s13);
-  y3 = cadd(d02, mul_pi(d13));
-}
-
-// One in-place Stockham pass of radix R over M points with sub-transform size
-// Ns: butterfly j (k = j mod Ns) reads x_r = buf[j + r M/R], twiddles x_r by
-// w^r with w = e^{-2 pi i k / (R Ns)}, and writes its length-R DFT to
-// buf[(j - k) R + k + r Ns].  A length-8 DFT is two length-4 DFTs of
-// x_k + x_{k+4} and (x_k - x_{k+4}) e^{-2 pi i k / 8}.
-template <int R>
-__device__ void stockham_pass(double2 *buf, const double2 *__restrict__ T, int M, int Ns) {
-  constexpr int B = 4096 / R / kPsThreads;  // butterflies per thread at M = 4096
-  const int nb = M / R;
-  const int step = (M / (R * Ns)) * (kPsMaxN / 2 / M);  // stride in the 4096-point table
-  double2 y[B][R];
-#pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int j = (int)threadIdx.x + b * kPsThreads;
-    if (j < nb) {
-      const int k = j & (Ns - 1);
-      const double2 w = T[k * step];
-      double2 x[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) x[r] = buf[j + r * nb];
-      if constexpr (R == 8) {
-        const double2 w2 = cmul(w, w), w3 = cmul(w2, w), w4 = cmul(w2, w2);
-        const double2 w5 = cmul(w4, w), w6 = cmul(w3, w3), w7 = cmul(w6, w);
-        x[1] = cmul(x[1], w);
-        x[2] = cmul(x[2], w2);
-        x[3] = cmul(x[3], w3);
-        x[4] = cmul(x[4], w4);
-        x[5] = cmul(x[5], w5);
-        x[6] = cmul(x[6], w6);
-        x[7] = cmul(x[7], w7);
-        constexpr double h = 0.70710678118654752440;  // sqrt(1/2)
-        const double2 b0 = csub(x[0], x[4]);
-        const double2 t1 = csub(x[1], x[5]);
-        const double2 b1 = make_double2(h * (t1.x + t1.y), h * (t1.y - t1.x));  // * (1 - i)/sqrt2
-        const double2 b2 = mul_mi(csub(x[2], x[6]));
-        const double2 t3 = csub(x[3], x[7]);
-        const double2 b3 = make_double2(h * (t3.y - t3.x), -h * (t3.x + t3.y));  // * -(1 + i)/sqrt2
-        dft4(cadd(x[0], x[4]), cadd(x[1], x[5]), cadd(x[2], x[6]), cadd(x[3], x[7]), y[b][0],
-             y[b][2], y[b][4], y[b][6]);
-        dft4(b0, b1, b2, b3, y[b][1], y[b][3], y[b][5], y[b][7]);
-      } else if constexpr (R == 4) {
-        const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
-        dft4(x[0], cmul(x[1], w), cmul(x[2], w2), cmul(x[3], w3), y[b][0], y[b][1], y[b][2],
-             y[b][3]);
-      } else {
-        const double2 a1 = cmul(x[1], w);
-        y[b][0] = cadd(x[0], a1);
-        y[b][1] = csub(x[0], a1);
-      }
-    }
-  }
-  __syncthreads();  // every read of this pass is done
-#pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int j = (int)threadIdx.x + b * kPsThreads;
-    if (j < nb) {
-      const int k = j & (Ns - 1);
-      const int base = (j - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns] = y[b][r];
-    }
-  }
-  __syncthreads();
-}
-
 // Twiddle table of the largest transform, exp(-2 pi i t / 4096), t < 2048; the
 // table of a transform of M points is every (4096 / M)-th entry.
 constexpr int kTwMax = kPsMaxN / 2;
+static_assert(kTwMax == kFftTableLen, "one twiddle table serves every transform");
 __global__ void twiddle_kernel(double2 *__restrict__ T) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < kTwMax / 2) {
@@ -213,16 +131,7 @@ __global__ __launch_bounds__(kPsThreads) void flux_power_kernel(
     for (int j = threadIdx.x; j < M; j += kPsThreads) put(j, make_float2(f[2 * j], f[2 * j + 1]));
   }
   __syncthreads();
-  int Ns = 1;
-  while (Ns * 8 <= M) {
-    stockham_pass<8>(buf, Tg, M, Ns);
-    Ns *= 8;
-  }
-  if (Ns * 4 <= M) {
-    stockham_pass<4>(buf, Tg, M, Ns);
-    Ns *= 4;
-  }
-  if (Ns * 2 <= M) stockham_pass<2>(buf, Tg, M, Ns);
+  fft_batch<kPsThreads, kPsMaxN / 2>(buf, Tg, M, 0);
 
   // unpack the real spectrum: X_m = E_m + e^{-pi i m / M} O_m, m = 0 .. M
   double s1, c1;

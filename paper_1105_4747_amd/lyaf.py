@@ -7,6 +7,7 @@ stream.  If the library is missing or fails to load, every call raises.
 Functions mirror the C entry points:
   tau(...)                         -> lyaf_tau
   normalise_mean_flux(...)         -> lyaf_normalise_mean_flux
+  field_skewers(...)               -> lyaf_field_skewers
   normalise_mean_flux_backward(...)-> lyaf_normalise_mean_flux_backward
   tau_backward(...)                -> lyaf_tau_backward
   status_read(...)                 -> lyaf_status_read
@@ -42,13 +43,20 @@ EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_ba
             "lyaf_plan_create", "lyaf_plan_execute", "lyaf_plan_status", "lyaf_plan_describe",
             "lyaf_plan_destroy", "lyaf_instrument", "lyaf_instrument_backward",
             "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms", "lyaf_flux_pdf",
-            "lyaf_flux_power", "lyaf_kernel_timing", "lyaf_kernel_timing_read")
+            "lyaf_flux_power", "lyaf_kernel_timing", "lyaf_kernel_timing_read",
+            "lyaf_field_skewers")
 
 
 class InstrumentParams(ctypes.Structure):
     _fields_ = [("fwhm_kms", ctypes.c_double), ("bin_kms", ctypes.c_double),
                 ("v_start_kms", ctypes.c_double), ("noise_sigma", ctypes.c_double),
                 ("window_k", ctypes.c_double)]
+
+
+class FieldParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("box", ctypes.c_double), ("amp", ctypes.c_double),
+                ("k_F", ctypes.c_double), ("E_plus", ctypes.c_double), ("dk", ctypes.c_double),
+                ("n_table", ctypes.c_int64)]
 
 
 class LyafError(RuntimeError):
@@ -135,6 +143,10 @@ def load():
         lib.lyaf_flux_pdf.restype = i32
         lib.lyaf_flux_power.argtypes = [i64, pi64, vp, vp, dbl, vp, vp]
         lib.lyaf_flux_power.restype = i32
+        pi32 = ctypes.POINTER(ctypes.c_int32)
+        lib.lyaf_field_skewers.argtypes = [ctypes.POINTER(FieldParams), vp, vp, i64, pi32, pi32,
+                                           vp, vp, vp]
+        lib.lyaf_field_skewers.restype = i32
         lib.lyaf_kernel_timing.argtypes = [i32]
         lib.lyaf_kernel_timing.restype = i32
         lib.lyaf_kernel_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), pi64]
@@ -292,6 +304,28 @@ def flux_power(F, dv, offsets, mean_F, out, stream=None):
                                   float(mean_F), _ptr(out), _stream(stream)),
            "lyaf_flux_power")
     return out
+
+
+def field_skewers(modes, pk, sx, sy, delta_b, v_z, n, box, amp, k_F, E_plus, dk,
+                  stream=None):
+    """lyaf_field_skewers: delta_b and v_z (float32 device [S, n]) on the
+    sight-lines (sx[s], sy[s]) of the field whose Gaussian half-spectrum is
+    ``modes`` (complex64 device [n, n, n/2+1]) and power table ``pk`` (float64
+    device, P at |k| = j dk); eqs. (1) and (3)."""
+    import torch
+    assert modes.dtype == torch.complex64 and pk.dtype == torch.float64
+    x = np.ascontiguousarray(np.asarray(sx, dtype=np.int32))
+    y = np.ascontiguousarray(np.asarray(sy, dtype=np.int32))
+    if x.shape != y.shape:
+        raise ValueError("sx and sy differ in length")
+    fp = FieldParams(int(n), float(box), float(amp), float(k_F), float(E_plus), float(dk),
+                     int(pk.numel()))
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    _check(load().lyaf_field_skewers(ctypes.byref(fp), _ptr(modes), _ptr(pk), len(x),
+                                     x.ctypes.data_as(pi32), y.ctypes.data_as(pi32),
+                                     _ptr(delta_b), _ptr(v_z), _stream(stream)),
+           "lyaf_field_skewers")
+    return delta_b, v_z
 
 
 def status_read(stream=None) -> int:

@@ -295,3 +295,99 @@ def config4(seed: int = 4, nx: int = 512, ny: int = 512, nz: int = 4096,
     return Workload(f"C4 box {nx}x{ny}x{nz}", D, v, _offsets(lengths),
                     np.full(S, 2.0, np.float32), np.full(S, 1.5e4, np.float32),
                     np.full(S, 1.5, np.float32), 0.8, 6.0)
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the skewer-only field synthesis (Section 2.1, eqs. 1 and 3).
+
+# Cosmology of the paper's calibration run (Section 2): h, Omega_m, n_s.
+H_LITTLE, OMEGA_M, N_S = 0.72, 0.26, 0.96
+K_F_MPC = 6.5  # filtering wavenumber of eq. (1), Mpc^-1 (Section 2.1)
+# E_+ = H(z) f / (1 + z) at z = 3 with H(3) = 300.2 km/s/Mpc and
+# f = Omega_m(z)^0.55 = 0.976; the growth factor is folded into the amplitude.
+E_PLUS_Z3 = 300.2 * 0.976 / 4.0
+
+
+@dataclasses.dataclass
+class FieldInputs:
+    name: str
+    n: int                 # grid points per side
+    modes: object          # complex64 [n, n, n/2+1] (numpy, or a torch tensor)
+    pk: np.ndarray         # float64 [n_table]: P at |k| = j dk
+    dk: float              # Mpc^-1
+    amp: float
+    box: float             # Mpc
+    k_F: float             # Mpc^-1
+    E_plus: float          # km/s Mpc
+    sx: np.ndarray         # int32 [S]
+    sy: np.ndarray         # int32 [S]
+
+
+def bbks_power_table(n: int, box: float, n_table: int = 4096):
+    """Linear power shape P(k) = k^n_s T(q)^2 with the BBKS transfer function,
+    T(q) = ln(1 + 2.34 q) / (2.34 q) [1 + 3.89 q + (16.1 q)^2 + (5.46 q)^3 +
+    (6.71 q)^4]^(-1/4), q = k / (Omega_m h^2) (k in Mpc^-1): a closed-form
+    stand-in for the Eisenstein & Hu transfer function the paper uses, which is
+    not available here.  Tabulated at j dk up to just past the grid's largest
+    |k| = sqrt(3) pi n / box.  Returns (table float64 [n_table], dk)."""
+    kmax = np.sqrt(3.0) * np.pi * n / box
+    dk = kmax * 1.001 / (n_table - 1)
+    k = np.arange(n_table) * dk
+    q = k / (OMEGA_M * H_LITTLE ** 2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        T = np.where(q > 0, np.log1p(2.34 * q) / (2.34 * q), 1.0) * (
+            1 + 3.89 * q + (16.1 * q) ** 2 + (5.46 * q) ** 3 + (6.71 * q) ** 4) ** -0.25
+    return (k ** N_S * T ** 2).astype(np.float64), float(dk)
+
+
+def _unit_rms_amp(n, box, pk, dk):
+    """Amplitude that gives delta_DM unit variance for modes of E|g|^2 = n^3
+    (the transform of unit white noise): Var = n^-3 sum over the full spectrum
+    of amp^2 P(|k|), counted on the half-spectrum with weight 2 for 0 < mz < n/2."""
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    mz = np.arange(n // 2 + 1, dtype=np.float64)
+    w = np.where((mz == 0) | (mz == n // 2), 1.0, 2.0)
+    f = 2 * np.pi / box
+    tot = 0.0
+    for a in m:
+        k = f * np.sqrt(a * a + m[:, None] ** 2 + mz[None, :] ** 2)
+        tot += float(np.sum(w[None, :] * np.interp(k, np.arange(pk.size) * dk, pk, right=0.0)))
+    return 1.0 / np.sqrt(tot / n ** 3)
+
+
+def field_columns(n: int, n_lines: int, seed: int):
+    """n_lines distinct random columns (sx, sy) of an n x n grid, int32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.choice(n * n, size=n_lines, replace=False)
+    return (c // n).astype(np.int32), (c % n).astype(np.int32)
+
+
+def field_modes_white(n: int, seed: int, device="cpu"):
+    """The half-spectrum of unit-variance real white noise on an n^3 grid
+    (torch.fft.rfftn of seeded torch normals): complex64 torch tensor
+    [n, n, n/2+1] on ``device``, E|g|^2 = n^3, Hermitian where a real field's
+    spectrum is."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    z = torch.randn((n, n, n), generator=gen, device=device, dtype=torch.float32)
+    g = torch.fft.rfftn(z)
+    del z
+    return g.to(torch.complex64).contiguous()
+
+
+def field_synthesis_workload(n: int = 1024, n_lines: int = 6250, seed: int = 7,
+                             device="cpu") -> FieldInputs:
+    """Sight-lines through a box of the paper's Gpc-run cell size (1 Gpc /
+    4096 = 0.244 Mpc, so 250 Mpc at n = 1024), at the paper's sight-line
+    density (100,000 per 4096^2 columns: 6,250 per 1024^2), k_F = 6.5 Mpc^-1,
+    E_+ at z = 3, the BBKS power shape scaled to unit rms delta_DM, modes from
+    real white noise (generated with torch on ``device``)."""
+    box = n * 1000.0 / 4096.0
+    pk, dk = bbks_power_table(n, box)
+    amp = _unit_rms_amp(n, box, pk, dk)
+    sx, sy = field_columns(n, n_lines, seed)
+    return FieldInputs(f"field synthesis {n}^3, {n_lines} sight-lines", n,
+                       field_modes_white(n, seed, device), pk, dk, amp, box, K_F_MPC,
+                       E_PLUS_Z3, sx, sy)
+

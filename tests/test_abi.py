@@ -247,3 +247,50 @@ def test_kernel_timing_records_nothing_when_idle(lib):
     assert L.kernel_timing_read("tau") == (0.0, 0)
     L.kernel_timing(False)
     assert L.kernel_timing_read("tau") == (0.0, 0)
+
+
+def _field_params(**kw):
+    d = dict(n=16, box=10.0, amp=1.0, k_F=2.0, E_plus=50.0, dk=0.1, n_table=8)
+    d.update(kw)
+    return L.FieldParams(d["n"], d["box"], d["amp"], d["k_F"], d["E_plus"], d["dk"],
+                         d["n_table"])
+
+
+@pytest.mark.parametrize("kw", [dict(n=2), dict(n=12), dict(n=4096), dict(box=0.0),
+                                dict(box=float("inf")), dict(amp=float("nan")),
+                                dict(k_F=0.0), dict(k_F=-1.0), dict(E_plus=float("inf")),
+                                dict(dk=0.0), dict(n_table=0)])
+def test_field_skewers_rejects_bad_parameters(lib, kw):
+    p = ctypes.c_void_p(0x1000)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    xs = (ctypes.c_int32 * 2)(0, 1)
+    fp = _field_params(**kw)
+    assert lib.lyaf_field_skewers(ctypes.byref(fp), p, p, 2, ctypes.cast(xs, pi32),
+                                  ctypes.cast(xs, pi32), p, p, None) == L.LYAF_EINVAL
+
+
+def test_field_skewers_rejects_bad_columns_and_pointers(lib):
+    p = ctypes.c_void_p(0x1000)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    good = (ctypes.c_int32 * 2)(0, 15)
+    f = lib.lyaf_field_skewers
+    fp = _field_params()
+    for bad in ((0, 16), (-1, 3)):
+        b = (ctypes.c_int32 * 2)(*bad)
+        assert f(ctypes.byref(fp), p, p, 2, ctypes.cast(b, pi32), ctypes.cast(good, pi32),
+                 p, p, None) == L.LYAF_EINVAL
+        assert f(ctypes.byref(fp), p, p, 2, ctypes.cast(good, pi32), ctypes.cast(b, pi32),
+                 p, p, None) == L.LYAF_EINVAL
+    gx = ctypes.cast(good, pi32)
+    assert f(None, p, p, 2, gx, gx, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(fp), None, p, 2, gx, gx, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(fp), p, None, 2, gx, gx, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(fp), p, p, 2, None, gx, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(fp), p, p, 2, gx, gx, None, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(fp), p, p, 2, gx, gx, p, None, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(fp), p, p, -1, gx, gx, p, p, None) == L.LYAF_EINVAL
+    # no sight-lines: nothing to do, no pointer is read
+    assert f(ctypes.byref(fp), None, None, 0, None, None, None, None, None) == L.LYAF_OK
+    fp_inf = _field_params(k_F=float("inf"))  # no filter is allowed
+    assert f(ctypes.byref(fp_inf), None, None, 0, None, None, None, None, None) == L.LYAF_OK
+
