@@ -119,10 +119,28 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out,
  *   A_dev:     DEVICE double, written with A.
  * No host synchronisation: a missing root or a non-converged iteration is
  * reported through the status word (A is then left at its last iterate).
- * Errors: EINVAL (n_pix < 0, null pointers, target_F not in (0, 1)), EDEVICE,
- * ENOMEM. */
+ * Errors: EINVAL (n_pix <= 0 or > 2^48, null pointers, target_F not in (0, 1)),
+ * EDEVICE, ENOMEM. */
 int lyaf_normalise_mean_flux(int64_t n_pix, float *tau_inout, float *F_out,
                              double target_F, double *A_dev, void *stream);
+
+/* Allocation-free lyaf_normalise_mean_flux, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as
+ * lyaf_normalise_mean_flux (bitwise-identical tau' and F), plus:
+ *   status_dev: DEVICE uint32 or NULL; LYAF_STATUS_* bits of this call are
+ *               OR'd into it (the caller clears it).  NULL discards them.
+ * It calls no hipMalloc, hipFree or other allocating routine and takes no
+ * library lock: its scratch (partial sums, the root-find sample and states,
+ * LYAF_NORM_NOALLOC_SCRATCH_BYTES per device) is one static device array that
+ * every call on that device shares, set up on the first call on the device.
+ * Calls that overlap in time on one device (different streams or threads)
+ * therefore race and give wrong results; serialise them.  Any n_pix up to
+ * 2^48 fits the fixed scratch (larger sizes: EINVAL). */
+#define LYAF_NORM_NOALLOC_SCRATCH_BYTES 131840
+int lyaf_normalise_mean_flux_noalloc(int64_t n_pix, float *tau_inout, float *F_out,
+                                     double target_F, double *A_dev, uint32_t *status_dev,
+                                     void *stream);
 
 /* Backward of lyaf_normalise_mean_flux.  With G_p = dL/dtau'_p - F_p dL/dF_p:
  *   implicit_A = 0: dL/dtau_p = A G_p (A held fixed)

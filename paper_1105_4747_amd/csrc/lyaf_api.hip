@@ -561,7 +561,7 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out, voi
 
 int lyaf_normalise_mean_flux(int64_t n_pix, float *tau_inout, float *F_out, double target_F,
                              double *A_dev, void *stream) {
-  if (n_pix <= 0 || !tau_inout || !A_dev) return LYAF_EINVAL;
+  if (n_pix <= 0 || n_pix > kMaxNormPixels || !tau_inout || !A_dev) return LYAF_EINVAL;
   if (!(target_F > 0.0 && target_F < 1.0)) return LYAF_EINVAL;
   if (F_out == tau_inout) return LYAF_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -572,6 +572,17 @@ int lyaf_normalise_mean_flux(int64_t n_pix, float *tau_inout, float *F_out, doub
   return map_err(timed("normalise", st, [&] {
     return launch_norm(n_pix, tau_inout, F_out, target_F, A_dev, *ws, st);
   }));
+}
+
+int lyaf_normalise_mean_flux_noalloc(int64_t n_pix, float *tau_inout, float *F_out,
+                                     double target_F, double *A_dev, uint32_t *status_dev,
+                                     void *stream) {
+  if (n_pix <= 0 || n_pix > kMaxNormPixels || !tau_inout || !A_dev) return LYAF_EINVAL;
+  if (!(target_F > 0.0 && target_F < 1.0)) return LYAF_EINVAL;
+  if (F_out == tau_inout) return LYAF_EINVAL;
+  // no workspace, no lock, no timing events: only kernel launches
+  return map_err(launch_norm_noalloc(n_pix, tau_inout, F_out, target_F, A_dev, status_dev,
+                                     (hipStream_t)stream));
 }
 
 int lyaf_normalise_mean_flux_backward(int64_t n_pix, const float *tau_raw, const double *A_dev,

@@ -92,6 +92,9 @@ constexpr int kSampleN = 16384;         // pixels the root-find samples first
 // two partial buffers.
 constexpr int64_t kPartialsDoubles = 2 * kPartStride * kMaxPartialBlocks + kSampleN / 2;
 constexpr double kNormAcceptStep = 1e-5;
+// Largest batch of the mean-flux root-find: the sample index k P / 16384 is
+// formed in int64 (2^48 pixels is a petabyte of tau, far beyond any device).
+constexpr int64_t kMaxNormPixels = int64_t(1) << 48;
 
 // Kernel-side view of a skewer batch.
 struct Batch {
@@ -126,6 +129,12 @@ hipError_t launch_tau_plain(const Batch &b, int64_t skewer, int64_t n, float *ta
                             hipStream_t st);
 hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F,
                        double *A_dev, Workspace &ws, hipStream_t st);
+// lyaf_normalise_mean_flux_noalloc: the same kernels with their scratch in a
+// static device array of kNormNoAllocScratchBytes per device (no allocation);
+// status may be null (the bits then land in the array and are not reported).
+constexpr size_t kNormNoAllocScratchBytes = LYAF_NORM_NOALLOC_SCRATCH_BYTES;
+hipError_t launch_norm_noalloc(int64_t n_pix, float *tau, float *F, double target_F,
+                               double *A_dev, uint32_t *status, hipStream_t st);
 hipError_t launch_norm_backward(int64_t n_pix, const float *tau, const double *A_dev,
                                 const float *gF, const float *gT, int implicit_A,
                                 float *out, Workspace &ws, hipStream_t st);

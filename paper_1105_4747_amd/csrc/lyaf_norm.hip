@@ -33,6 +33,8 @@
 // reproducible.
 #include <math.h>
 
+#include <mutex>
+
 #include "lyaf_internal.h"
 
 namespace lyaf {
@@ -456,23 +458,82 @@ static int norm_grid(int64_t pixels) {  // backward reductions
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxPartialBlocks));
 }
 
-hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F, double *A_dev,
-                       Workspace &ws, hipStream_t st) {
+hipError_t launch_norm_buffers(int64_t n_pix, float *tau, float *F, double target_F,
+                               double *A_dev, double *partials, NormState *norm,
+                               uint32_t *status, hipStream_t st) {
   int64_t g = (n_pix + kPassThreads * 16 - 1) / (kPassThreads * 16);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxPartialBlocks));
-  float *sample = reinterpret_cast<float *>(ws.partials + 2 * kPartStride * kMaxPartialBlocks);
+  float *sample = reinterpret_cast<float *>(partials + 2 * kPartStride * kMaxPartialBlocks);
   hipLaunchKernelGGL(norm_gather_kernel, dim3(kSampleN / kGatherThreads), dim3(kGatherThreads),
                      0, st, tau, n_pix, sample);
   hipLaunchKernelGGL(norm_sample_kernel, dim3(1), dim3(kSampleThreads), 0, st, sample, n_pix,
-                     target_F, ws.norm);
+                     target_F, norm);
   for (int k = 0; k < kNormPasses; ++k)
     hipLaunchKernelGGL(norm_pass_kernel, dim3(grid), dim3(kPassThreads), 0, st, tau, n_pix,
-                       ws.partials, ws.norm + k, ws.norm + k + 1, ws.status);
+                       partials, norm + k, norm + k + 1, status);
   const int fgrid = (int)std::min<int64_t>((n_pix + 4095) / 4096, 2048);
   hipLaunchKernelGGL(norm_finalise_kernel, dim3(std::max(fgrid, 1)), dim3(kNormThreads), 0, st,
-                     tau, F, n_pix, ws.partials, ws.norm + kNormPasses,
-                     ws.norm + kNormPasses + 1, A_dev, ws.status);
+                     tau, F, n_pix, partials, norm + kNormPasses, norm + kNormPasses + 1, A_dev,
+                     status);
   return hipGetLastError();
+}
+
+hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F, double *A_dev,
+                       Workspace &ws, hipStream_t st) {
+  return launch_norm_buffers(n_pix, tau, F, target_F, A_dev, ws.partials, ws.norm, ws.status,
+                             st);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the root-find's scratch (the FP64 partials of two
+// passes and the 16384-pixel sample, the iteration states, and a status word
+// for callers that pass none) lives in one file-scope device array instead of
+// a workspace.  The passes use at most kMaxPartialBlocks workgroups and a
+// fixed sample whatever n_pix is, so this fixed size serves every batch.  In
+// host code `scratch` names a host-side stand-in, not device memory: the
+// device address comes from hipGetSymbolAddress, once per device (each device
+// holds its own copy of the array).
+constexpr size_t kNoAllocPartialsBytes = sizeof(double) * (size_t)kPartialsDoubles;
+constexpr size_t kNoAllocStatesOffset = (kNoAllocPartialsBytes + 255) / 256 * 256;
+constexpr size_t kNoAllocStatusOffset =
+    (kNoAllocStatesOffset + sizeof(NormState) * (kNormPasses + 2) + 255) / 256 * 256;
+constexpr size_t kNoAllocScratchBytes = kNoAllocStatusOffset + 256;
+static_assert(kNoAllocScratchBytes == kNormNoAllocScratchBytes,
+              "scratch size declared in lyaf_internal.h");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+hipError_t norm_noalloc_scratch(void **ptr_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr_out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_norm_noalloc(int64_t n_pix, float *tau, float *F, double target_F,
+                               double *A_dev, uint32_t *status, hipStream_t st) {
+  void *base = nullptr;
+  hipError_t e = norm_noalloc_scratch(&base);
+  if (e != hipSuccess) return e;
+  unsigned char *b = static_cast<unsigned char *>(base);
+  double *partials = reinterpret_cast<double *>(b);
+  NormState *norm = reinterpret_cast<NormState *>(b + kNoAllocStatesOffset);
+  uint32_t *st_word = status ? status : reinterpret_cast<uint32_t *>(b + kNoAllocStatusOffset);
+  return launch_norm_buffers(n_pix, tau, F, target_F, A_dev, partials, norm, st_word, st);
 }
 
 // ---------------------------------------------------------------------------

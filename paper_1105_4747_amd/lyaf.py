@@ -7,6 +7,7 @@ stream.  If the library is missing or fails to load, every call raises.
 Functions mirror the C entry points:
   tau(...)                         -> lyaf_tau
   normalise_mean_flux(...)         -> lyaf_normalise_mean_flux
+  normalise_mean_flux_noalloc(...) -> lyaf_normalise_mean_flux_noalloc
   field_skewers(...)               -> lyaf_field_skewers
   normalise_mean_flux_backward(...)-> lyaf_normalise_mean_flux_backward
   tau_backward(...)                -> lyaf_tau_backward
@@ -44,7 +45,7 @@ EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_ba
             "lyaf_plan_destroy", "lyaf_instrument", "lyaf_instrument_backward",
             "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms", "lyaf_flux_pdf",
             "lyaf_flux_power", "lyaf_kernel_timing", "lyaf_kernel_timing_read",
-            "lyaf_field_skewers")
+            "lyaf_normalise_mean_flux_noalloc", "lyaf_field_skewers")
 
 
 class InstrumentParams(ctypes.Structure):
@@ -108,6 +109,8 @@ def load():
         lib.lyaf_tau.restype = i32
         lib.lyaf_normalise_mean_flux.argtypes = [i64, vp, vp, dbl, vp, vp]
         lib.lyaf_normalise_mean_flux.restype = i32
+        lib.lyaf_normalise_mean_flux_noalloc.argtypes = [i64, vp, vp, dbl, vp, vp, vp]
+        lib.lyaf_normalise_mean_flux_noalloc.restype = i32
         lib.lyaf_normalise_mean_flux_backward.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp]
         lib.lyaf_normalise_mean_flux_backward.restype = i32
         lib.lyaf_tau_backward.argtypes = [PS, PP, vp, vp, vp, vp, vp, vp]
@@ -213,6 +216,18 @@ def normalise_mean_flux(tau_inout, F_out, target_F, A_out, stream=None):
     _check(load().lyaf_normalise_mean_flux(tau_inout.numel(), _ptr(tau_inout), _ptr(F_out),
                                            float(target_F), _ptr(A_out), _stream(stream)),
            "lyaf_normalise_mean_flux")
+
+
+NORM_NOALLOC_SCRATCH_BYTES = 131840  # LYAF_NORM_NOALLOC_SCRATCH_BYTES
+
+
+def normalise_mean_flux_noalloc(tau_inout, F_out, target_F, A_out, status=None, stream=None):
+    """lyaf_normalise_mean_flux_noalloc: as normalise_mean_flux, with the
+    library's scratch in a static device array (no allocation); LYAF_STATUS_*
+    bits are OR'd into ``status`` (uint32/int32 device scalar) when given."""
+    _check(load().lyaf_normalise_mean_flux_noalloc(
+        tau_inout.numel(), _ptr(tau_inout), _ptr(F_out), float(target_F), _ptr(A_out),
+        _ptr(status), _stream(stream)), "lyaf_normalise_mean_flux_noalloc")
 
 
 def normalise_mean_flux_backward(tau_raw, A, grad_F, grad_tau_scaled, implicit_A, out,

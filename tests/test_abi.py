@@ -94,6 +94,16 @@ def test_normalise_rejects_bad_arguments(lib):
     assert f(10, p, p, 0.5, A, None) == L.LYAF_EINVAL       # F aliases tau
     for F in (0.0, 1.0, -0.1, 1.5, float("nan")):
         assert f(10, p, q, F, A, None) == L.LYAF_EINVAL
+    n = lib.lyaf_normalise_mean_flux_noalloc
+    assert n(0, p, q, 0.5, A, None, None) == L.LYAF_EINVAL
+    assert n(-3, p, q, 0.5, A, None, None) == L.LYAF_EINVAL
+    assert n(10, None, q, 0.5, A, None, None) == L.LYAF_EINVAL
+    assert n(10, p, q, 0.5, None, None, None) == L.LYAF_EINVAL
+    assert n(10, p, p, 0.5, A, None, None) == L.LYAF_EINVAL
+    assert n((1 << 48) + 1, p, q, 0.5, A, None, None) == L.LYAF_EINVAL   # beyond the maximum
+    assert f((1 << 48) + 1, p, q, 0.5, A, None) == L.LYAF_EINVAL
+    for F in (0.0, 1.0, -0.1, 1.5, float("nan")):
+        assert n(10, p, q, F, A, None, None) == L.LYAF_EINVAL
     b = lib.lyaf_normalise_mean_flux_backward
     assert b(-1, p, A, None, None, 1, q, None) == L.LYAF_EINVAL
     assert b(10, None, A, None, None, 1, q, None) == L.LYAF_EINVAL
