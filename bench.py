@@ -293,6 +293,33 @@ def fields_section(L, torch, dev, fields, timed, reps):
                                                  "kernel": dom}}
 
 
+def power3d_section(L, torch, dev, fields, timed, reps):
+    """3D flux power reconstruction of eq. (7) (lyaf_flux_power_3d) from 6,250
+    sight-lines of 1024 pixels in a 1024^3 box, shells of the fundamental: the
+    whole call (HIP events), against HBM with the bytes of the grid-free method
+    (the row sums written and read once, the sight-line spectra, the input)."""
+    w = fields.power3d_workload()
+    print(f"bench: {w.name}", file=sys.stderr, flush=True)
+    n, S = w.n, len(w.sx)
+    H = n // 2 + 1
+    F = torch.from_numpy(w.F).to(dev)
+    nb = int(np.floor(np.sqrt(3) * n / 2)) + 1
+    outs = [torch.empty(nb, device=dev, dtype=torch.float64) for _ in range(4)]
+    call = lambda: L.flux_power_3d(F, w.mean_F, w.sx, w.sy, n, w.box, nb, *outs,
+                                   p_noise=w.p_noise)
+    t_call = timed(call, reps)
+    t_k = kernel_seconds(L, call, reps, "flux_power_3d")
+    if L.status_read() != 0:
+        raise RuntimeError("device status set in the 3D power section")
+    rows = len(np.unique(w.sy))
+    nbytes = 4.0 * S * n + 2 * 16.0 * S * H + 2 * 16.0 * n * rows * H + 8.0 * n * n
+    return {"workload": w.name, "n": n, "sight_lines": S, "rows_in_use": rows, "shells": nb,
+            "call_ms": round(t_call * 1e3, 4), "kernels_ms": round(t_k * 1e3, 4),
+            "modes_per_s": float(n) * n * H / t_call,
+            "method_bytes": int(nbytes),
+            "roofline": {**_hbm_roof(nbytes, t_k), "kernel": "every kernel of the call"}}
+
+
 def kernel_seconds(L, fn, reps, name):
     """Average duration (s) of the library's launches recorded under ``name``
     while ``fn`` runs ``reps`` times (HIP events the library records around
@@ -507,8 +534,11 @@ def main():
     ap.add_argument("--no-instrument", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--no-fields", action="store_true")
+    ap.add_argument("--no-power3d", action="store_true")
     ap.add_argument("--fields-only", action="store_true",
                     help="only run the field-synthesis section, for profiling")
+    ap.add_argument("--power3d-only", action="store_true",
+                    help="only run the 3D flux power section, for profiling")
     ap.add_argument("--stats-only", action="store_true",
                     help="only run the flux-statistics section (PDF, power spectrum), for profiling")
     ap.add_argument("--instrument-only", action="store_true",
@@ -566,6 +596,10 @@ def main():
         return
     if args.fields_only:
         print(json.dumps({"fields_only": True, **fields_section(
+            L, torch, dev, fields, timed, max(args.steps, 1))}), flush=True)
+        return
+    if args.power3d_only:
+        print(json.dumps({"power3d_only": True, **power3d_section(
             L, torch, dev, fields, timed, max(args.steps, 1))}), flush=True)
         return
     if args.adjoint_only or args.instrument_only or args.stats_only:
@@ -691,6 +725,9 @@ def main():
         extra["instrument"] = instrument_section(L, torch, dev, fields, timed, reps, F, dvt, w)
     if not args.no_fields:
         extra["field_synthesis"] = fields_section(L, torch, dev, fields, timed, reps)
+        torch.cuda.empty_cache()
+    if not args.no_power3d:
+        extra["flux_power_3d"] = power3d_section(L, torch, dev, fields, timed, reps)
         torch.cuda.empty_cache()
     if not args.no_stats:
         plan.execute()  # F of this workload

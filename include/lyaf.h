@@ -310,6 +310,48 @@ int lyaf_field_skewers(const lyaf_field_params *fp, const void *modes, const dou
                        int64_t n_lines, const int32_t *sx, const int32_t *sy, float *delta_b,
                        float *v_z, void *stream);
 
+/* ---- 3D flux power spectrum from sight-lines (Section 6.2, eq. 7) ----
+ *
+ * A mock survey's S sight-lines of n pixels run along z through the columns
+ * (sx[s], sy[s]) of an n^3 periodic grid of side L.  The flux contrast
+ * delta_s(z) = F_s(z) / mean_F - 1 of each sits in its column with weight w_s
+ * (1 in the paper); the rest of the box is empty.  With unnormalised DFTs
+ *   G_s(mz)   = sum_z delta_s(z) e^{-2 pi i mz z / n},
+ *   W(mx, my) = sum_s w_s e^{-2 pi i (mx sx_s + my sy_s) / n},
+ *   D(m)      = sum_s w_s G_s(mz) e^{-2 pi i (mx sx_s + my sy_s) / n},
+ * the reconstruction of eq. (7) is
+ *   P_true(m) = P_box(m) - [P_1D(mz) + p_noise] P_2D,w(mx, my),
+ *   P_box = L^3 n^-6 |D|^2,  P_1D = L n^-2 mean_s |G_s|^2,  P_2D,w = L^2 n^-4 |W|^2
+ * (the subtracted term equals P_box when every sight-line carries the same
+ * spectrum: the aliasing it removes).  The modes of the half-spectrum
+ * (mz = 0 .. n/2, weight 2 for 0 < mz < n/2, which stand for their conjugate
+ * partners) are averaged in spherical shells of the fundamental wavenumber:
+ * shell b holds b <= |m| < b + 1, |m| = sqrt(mx^2 + my^2 + mz^2), k = 2 pi m / L.
+ * FP64 throughout; the shell sums are FP64 atomics, so repeated calls agree to
+ * rounding, not bitwise. */
+typedef struct {
+  int64_t n;        /* pixels per sight-line = grid side: a power of two, 4 .. 2048 */
+  double box;       /* side L (> 0, finite) */
+  double mean_F;    /* mean flux defining the contrast (> 0, finite) */
+  double p_noise;   /* flat 1D noise power P_N (>= 0, finite; 0 for noiseless flux) */
+  int64_t n_bins;   /* shells (>= 1); shells past sqrt(3) n / 2 are empty */
+} lyaf_power3d_params;
+
+/*   F:       DEVICE float [n_lines][n], sight-line s at s*n.
+ *   sx, sy:  HOST int32 [n_lines], columns in 0 .. n-1 (repeats add up).
+ *   weights: DEVICE double [n_lines], or NULL for unit weights.
+ *   counts, k_mean, p_true, p_box: DEVICE double [n_bins], written: each
+ *     shell's mode count, mean |k|, mean P_true and mean P_box (0 for empty
+ *     shells).
+ * The library keeps a workspace of 16 (n_lines + n R)(n/2+1) + 8 n^2 bytes and
+ * a few MB of shell partials, R the number of distinct sy values (about 8.7 GB
+ * at n = 1024 with every row in use).  Errors: EINVAL (host checks above;
+ * n_lines >= 1), EDEVICE, ENOMEM. */
+int lyaf_flux_power_3d(const lyaf_power3d_params *pp, int64_t n_lines, const float *F,
+                       const int32_t *sx, const int32_t *sy, const double *weights,
+                       double *counts, double *k_mean, double *p_true, double *p_box,
+                       void *stream);
+
 /* ---- plans: the whole forward, tuned and captured once, replayed many times ----
  *
  * Section 2.3 applies the same steps to every spectrum of a survey: eq. (6) per
@@ -370,7 +412,8 @@ int lyaf_status_read(void *stream, uint32_t *device_status);
  *                persistent launch); "tau_plain" the plain full-sum kernels
  *   "normalise", "normalise_backward", "tau_adjoint", "instrument",
  *   "instrument_backward", "flux_pdf", "flux_power",
- *   "field_ky", "field_kx", "field_z" (the three kernels of lyaf_field_skewers).
+ *   "field_ky", "field_kx", "field_z" (the three kernels of lyaf_field_skewers),
+ *   "flux_power_3d" (every kernel of lyaf_flux_power_3d).
  * Launches under stream capture (plans, caller graphs) are not recorded, and
  * recording stops after 65536 launches.  lyaf_kernel_timing(0) stops and
  * clears.  lyaf_kernel_timing_read waits for the recorded launches of `name`,

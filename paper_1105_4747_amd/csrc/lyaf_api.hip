@@ -776,6 +776,68 @@ int lyaf_field_skewers(const lyaf_field_params *fp, const void *modes, const dou
   return map_err(timed("field_z", st, [&] { return launch_field_z(a, (int)n_lines, st); }));
 }
 
+int lyaf_flux_power_3d(const lyaf_power3d_params *pp, int64_t n_lines, const float *F,
+                       const int32_t *sx, const int32_t *sy, const double *weights,
+                       double *counts, double *k_mean, double *p_true, double *p_box,
+                       void *stream) {
+  if (!pp) return LYAF_EINVAL;
+  const int64_t n = pp->n;
+  if (n < 4 || n > kP3dMaxN || (n & (n - 1)) != 0) return LYAF_EINVAL;
+  if (!(pp->box > 0.0) || !isfinite(pp->box)) return LYAF_EINVAL;
+  if (!(pp->mean_F > 0.0) || !isfinite(pp->mean_F)) return LYAF_EINVAL;
+  if (!(pp->p_noise >= 0.0) || !isfinite(pp->p_noise)) return LYAF_EINVAL;
+  if (pp->n_bins < 1 || pp->n_bins > INT32_MAX) return LYAF_EINVAL;
+  if (n_lines < 1 || n_lines > INT32_MAX || !F || !sx || !sy) return LYAF_EINVAL;
+  if (!counts || !k_mean || !p_true || !p_box) return LYAF_EINVAL;
+  for (int64_t s = 0; s < n_lines; ++s)
+    if (sx[s] < 0 || sx[s] >= n || sy[s] < 0 || sy[s] >= n) return LYAF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace *ws = nullptr;
+  int rc = get_ws(st, &ws);
+  if (rc) return rc;
+  HostFieldPlan *hp = nullptr;
+  if ((rc = ensure_field_plan(ws, n, n_lines, sx, sy, &hp))) return rc;
+  if ((rc = ensure_twiddles(ws, st))) return rc;
+  const int64_t H = n / 2 + 1;
+  const int nb = p3d_shell_bins((int)n, (int)pp->n_bins);
+  int y_grid = 0;
+  hipError_t e;
+  if ((e = p3d_kernel_attributes((int)n, nb, &y_grid)) != hipSuccess) return map_err(e);
+  const int C = p3d_y_columns((int)n);
+  y_grid = (int)std::min<int64_t>(y_grid, n * ((H + C - 1) / C));
+  const int64_t n_c = n_lines * H + n * (int64_t)hp->n_rows * H;  // G, D1
+  const int64_t n_r = H + n * n + (int64_t)y_grid * 4 * nb;      // P1d, P2d, shells
+  if ((e = grow_dev(ws->p3d_c, ws->p3d_c_cap, n_c)) != hipSuccess ||
+      (e = grow_dev(ws->p3d_r, ws->p3d_r_cap, n_r)) != hipSuccess)
+    return map_err(e);
+  P3dArgs a;
+  a.F = F;
+  a.w = weights;
+  a.n = (int)n;
+  a.H = (int)H;
+  a.n_rows = hp->n_rows;
+  a.n_lines = (int)n_lines;
+  a.n_bins = (int)pp->n_bins;
+  a.inv_mean = 1.0 / pp->mean_F;
+  a.L = pp->box;
+  a.p_noise = pp->p_noise;
+  a.rows = hp->d_rows;
+  a.row_first = hp->d_first;
+  a.lines = hp->d_lines;
+  a.G = ws->p3d_c;
+  a.D1 = ws->p3d_c + n_lines * H;
+  a.P1d = ws->p3d_r;
+  a.P2d = ws->p3d_r + H;
+  a.shells = ws->p3d_r + H + n * n;
+  a.counts = counts;
+  a.k_mean = k_mean;
+  a.p_true = p_true;
+  a.p_box = p_box;
+  a.twiddle = ws->ps_twiddle;
+  return map_err(timed("flux_power_3d", st, [&] { return launch_power3d(a, y_grid, st); }));
+}
+
 double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {
   return kSpeedOfLightKms * dlambda_angstrom / (kLymanAlphaAngstrom * (1.0 + z));
 }

@@ -83,6 +83,9 @@ struct Workspace {
   // then the mx-transformed sight-lines)
   float2 *field_T = nullptr;   int64_t field_T_cap = 0;
   double2 *field_C = nullptr;  int64_t field_C_cap = 0;
+  // 3D flux power: complex (G, D1) and real (P1d, P2d, shell partials) buffers
+  double2 *p3d_c = nullptr;    int64_t p3d_c_cap = 0;
+  double *p3d_r = nullptr;     int64_t p3d_r_cap = 0;
 };
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
@@ -194,6 +197,33 @@ hipError_t launch_field_ky(const FieldArgs &a, hipStream_t st);
 hipError_t launch_field_kx(const FieldArgs &a, int n_groups, hipStream_t st);
 hipError_t launch_field_z(const FieldArgs &a, int n_lines, hipStream_t st);
 constexpr int kFieldLinesPerGroup = 8;
+// 3D flux power spectrum of eq. (7) from sight-lines.
+constexpr int kP3dMaxN = 2048;        // pixels per sight-line = grid side
+constexpr int kP3dMaxLds = 160 * 1024;  // LDS of one workgroup
+struct P3dArgs {
+  const float *F;         // device [S][n] flux
+  const double *w;        // device [S] weights or null (all 1)
+  int n, H;               // grid side and n/2 + 1
+  int n_rows, n_lines, n_bins;
+  double inv_mean;        // 1 / Fbar
+  double L, p_noise;      // box side, flat 1D noise power
+  const int *rows;        // device [n_rows]: y of each row in use
+  const int *row_first;   // device [n_rows + 1]: the row's sight-lines in `lines`
+  const int2 *lines;      // device [S]: (sight-line, x), grouped by row
+  double2 *G;             // device [S][H]: the sight-lines' transforms
+  double *P1d;            // device [H]
+  double *P2d;            // device [n][n] (mx, my)
+  double2 *D1;            // device [n][n_rows][H]: sum over a row's sight-lines
+  double *shells;         // device [workgroups][4][shells]
+  double *counts, *k_mean, *p_true, *p_box;  // device [n_bins] outputs
+  const double2 *twiddle;  // the shared FFT table
+};
+int p3d_shell_bins(int n, int n_bins);  // shells kept in LDS
+int p3d_y_columns(int n);               // mz per item of the y transform
+// Sets the kernels' LDS limits once per device; *y_grid: resident workgroups
+// of the y-transform kernel for grid side n and nb shells.
+hipError_t p3d_kernel_attributes(int n, int nb, int *y_grid);
+hipError_t launch_power3d(const P3dArgs &a, int y_grid, hipStream_t st);
 hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
                               const int64_t *item_base_dev, const float *g,
                               float *gdelta, float *gvpec, double *gT0,

@@ -9,6 +9,7 @@ Functions mirror the C entry points:
   normalise_mean_flux(...)         -> lyaf_normalise_mean_flux
   normalise_mean_flux_noalloc(...) -> lyaf_normalise_mean_flux_noalloc
   field_skewers(...)               -> lyaf_field_skewers
+  flux_power_3d(...)               -> lyaf_flux_power_3d
   normalise_mean_flux_backward(...)-> lyaf_normalise_mean_flux_backward
   tau_backward(...)                -> lyaf_tau_backward
   status_read(...)                 -> lyaf_status_read
@@ -45,7 +46,7 @@ EXPORTED = ("lyaf_tau", "lyaf_normalise_mean_flux", "lyaf_normalise_mean_flux_ba
             "lyaf_plan_destroy", "lyaf_instrument", "lyaf_instrument_backward",
             "lyaf_angstrom_to_kms", "lyaf_lya_lyb_path_kms", "lyaf_flux_pdf",
             "lyaf_flux_power", "lyaf_kernel_timing", "lyaf_kernel_timing_read",
-            "lyaf_normalise_mean_flux_noalloc", "lyaf_field_skewers")
+            "lyaf_normalise_mean_flux_noalloc", "lyaf_field_skewers", "lyaf_flux_power_3d")
 
 
 class InstrumentParams(ctypes.Structure):
@@ -58,6 +59,11 @@ class FieldParams(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("box", ctypes.c_double), ("amp", ctypes.c_double),
                 ("k_F", ctypes.c_double), ("E_plus", ctypes.c_double), ("dk", ctypes.c_double),
                 ("n_table", ctypes.c_int64)]
+
+
+class Power3dParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("box", ctypes.c_double), ("mean_F", ctypes.c_double),
+                ("p_noise", ctypes.c_double), ("n_bins", ctypes.c_int64)]
 
 
 class LyafError(RuntimeError):
@@ -150,6 +156,9 @@ def load():
         lib.lyaf_field_skewers.argtypes = [ctypes.POINTER(FieldParams), vp, vp, i64, pi32, pi32,
                                            vp, vp, vp]
         lib.lyaf_field_skewers.restype = i32
+        lib.lyaf_flux_power_3d.argtypes = [ctypes.POINTER(Power3dParams), i64, vp, pi32, pi32,
+                                           vp, vp, vp, vp, vp, vp]
+        lib.lyaf_flux_power_3d.restype = i32
         lib.lyaf_kernel_timing.argtypes = [i32]
         lib.lyaf_kernel_timing.restype = i32
         lib.lyaf_kernel_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), pi64]
@@ -341,6 +350,26 @@ def field_skewers(modes, pk, sx, sy, delta_b, v_z, n, box, amp, k_F, E_plus, dk,
                                      _ptr(delta_b), _ptr(v_z), _stream(stream)),
            "lyaf_field_skewers")
     return delta_b, v_z
+
+
+def flux_power_3d(F, mean_F, sx, sy, n, box, n_bins, counts, k_mean, p_true, p_box,
+                  weights=None, p_noise=0.0, stream=None):
+    """lyaf_flux_power_3d: the reconstruction of eq. (7) from the sight-lines
+    F (float32 device [S * n]) at columns (sx, sy), averaged in spherical shells
+    of the fundamental wavenumber; the four outputs are float64 device
+    [n_bins]: mode counts, mean |k|, mean P_true, mean P_box."""
+    x = np.ascontiguousarray(np.asarray(sx, dtype=np.int32))
+    y = np.ascontiguousarray(np.asarray(sy, dtype=np.int32))
+    if x.shape != y.shape:
+        raise ValueError("sx and sy differ in length")
+    pp = Power3dParams(int(n), float(box), float(mean_F), float(p_noise), int(n_bins))
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    _check(load().lyaf_flux_power_3d(ctypes.byref(pp), len(x), _ptr(F),
+                                     x.ctypes.data_as(pi32), y.ctypes.data_as(pi32),
+                                     _ptr(weights), _ptr(counts), _ptr(k_mean), _ptr(p_true),
+                                     _ptr(p_box), _stream(stream)),
+           "lyaf_flux_power_3d")
+    return counts, k_mean, p_true, p_box
 
 
 def status_read(stream=None) -> int:

@@ -391,3 +391,33 @@ def field_synthesis_workload(n: int = 1024, n_lines: int = 6250, seed: int = 7,
                        field_modes_white(n, seed, device), pk, dk, amp, box, K_F_MPC,
                        E_PLUS_Z3, sx, sy)
 
+
+# ---------------------------------------------------------------------------
+# Inputs of the 3D flux power spectrum reconstruction (Section 6.2, eq. 7).
+
+@dataclasses.dataclass
+class Power3dInputs:
+    name: str
+    n: int                 # grid points per side = pixels per sight-line
+    box: float             # Mpc
+    F: np.ndarray          # float32 [S * n], sight-line-major
+    mean_F: float
+    p_noise: float         # flat 1D noise power, Mpc
+    sx: np.ndarray         # int32 [S]
+    sy: np.ndarray         # int32 [S]
+
+
+def power3d_workload(n: int = 1024, n_lines: int = 6250, seed: int = 8,
+                     snr: float = 5.0) -> Power3dInputs:
+    """A mock survey in a box of the paper's Gpc-run cell size (250 Mpc at
+    n = 1024) at its sight-line density (6,250 distinct columns of 1024^2):
+    synthetic flux (lognormal optical depth, mean 0.35) on every sight-line,
+    the mean flux of the sample as Fbar, and the flat noise power of S/N = 5
+    per pixel, (1 / (S/N Fbar))^2 L / n."""
+    box = n * 1000.0 / 4096.0
+    F = synthetic_flux(np.full(n_lines, n, np.int64), seed)
+    mean_F = float(np.mean(F, dtype=np.float64))
+    sx, sy = field_columns(n, n_lines, seed)
+    p_noise = (1.0 / (snr * mean_F)) ** 2 * box / n
+    return Power3dInputs(f"3D flux power {n}^3, {n_lines} sight-lines", n, box, F, mean_F,
+                         p_noise, sx, sy)

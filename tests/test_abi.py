@@ -304,3 +304,41 @@ def test_field_skewers_rejects_bad_columns_and_pointers(lib):
     fp_inf = _field_params(k_F=float("inf"))  # no filter is allowed
     assert f(ctypes.byref(fp_inf), None, None, 0, None, None, None, None, None) == L.LYAF_OK
 
+
+def _p3d_params(**kw):
+    d = dict(n=16, box=10.0, mean_F=0.7, p_noise=0.0, n_bins=20)
+    d.update(kw)
+    return L.Power3dParams(d["n"], d["box"], d["mean_F"], d["p_noise"], d["n_bins"])
+
+
+@pytest.mark.parametrize("kw", [dict(n=2), dict(n=24), dict(n=4096), dict(box=0.0),
+                                dict(box=float("nan")), dict(mean_F=0.0),
+                                dict(mean_F=float("inf")), dict(p_noise=-1.0),
+                                dict(p_noise=float("inf")), dict(n_bins=0)])
+def test_flux_power_3d_rejects_bad_parameters(lib, kw):
+    p = ctypes.c_void_p(0x1000)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    xs = ctypes.cast((ctypes.c_int32 * 2)(0, 1), pi32)
+    pp = _p3d_params(**kw)
+    assert lib.lyaf_flux_power_3d(ctypes.byref(pp), 2, p, xs, xs, None, p, p, p, p,
+                                  None) == L.LYAF_EINVAL
+
+
+def test_flux_power_3d_rejects_bad_columns_and_pointers(lib):
+    p = ctypes.c_void_p(0x1000)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    g = ctypes.cast((ctypes.c_int32 * 2)(0, 15), pi32)
+    f = lib.lyaf_flux_power_3d
+    pp = _p3d_params()
+    for bad in ((0, 16), (-1, 3)):
+        b = ctypes.cast((ctypes.c_int32 * 2)(*bad), pi32)
+        assert f(ctypes.byref(pp), 2, p, b, g, None, p, p, p, p, None) == L.LYAF_EINVAL
+        assert f(ctypes.byref(pp), 2, p, g, b, None, p, p, p, p, None) == L.LYAF_EINVAL
+    assert f(None, 2, p, g, g, None, p, p, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(pp), 0, p, g, g, None, p, p, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(pp), 2, None, g, g, None, p, p, p, p, None) == L.LYAF_EINVAL
+    assert f(ctypes.byref(pp), 2, p, None, g, None, p, p, p, p, None) == L.LYAF_EINVAL
+    for k in range(4):
+        outs = [p, p, p, p]
+        outs[k] = None
+        assert f(ctypes.byref(pp), 2, p, g, g, None, *outs, None) == L.LYAF_EINVAL
