@@ -389,6 +389,8 @@ struct HostFieldPlan {
   int64_t h_rows_cap = 0, h_groups_cap = 0, h_lines_cap = 0, h_first_cap = 0;
   int *d_rows = nullptr; int4 *d_groups = nullptr; int2 *d_lines = nullptr;
   int *d_first = nullptr;  // [rows + 1]: first line of each row
+  int *h_row_of_y = nullptr, *d_row_of_y = nullptr;  // [n]: row of y, -1 if none
+  int64_t h_row_of_y_cap = 0, d_row_of_y_cap = 0;
   int64_t d_rows_cap = 0, d_groups_cap = 0, d_lines_cap = 0, d_first_cap = 0;
 };
 std::map<Workspace *, HostFieldPlan> g_field_plans;
@@ -424,7 +426,9 @@ int ensure_field_plan(Workspace *ws, int64_t n, int64_t S, const int32_t *sx, co
   }
   first.push_back((int)S);
   const int64_t nr = (int64_t)rows.size(), ng = (int64_t)groups.size();
-  if ((e = grow_host(hp.h_first, hp.h_first_cap, nr + 1)) != hipSuccess ||
+  if ((e = grow_host(hp.h_row_of_y, hp.h_row_of_y_cap, n)) != hipSuccess ||
+      (e = grow_dev(hp.d_row_of_y, hp.d_row_of_y_cap, n)) != hipSuccess ||
+      (e = grow_host(hp.h_first, hp.h_first_cap, nr + 1)) != hipSuccess ||
       (e = grow_dev(hp.d_first, hp.d_first_cap, nr + 1)) != hipSuccess ||
       (e = grow_host(hp.h_rows, hp.h_rows_cap, nr)) != hipSuccess ||
       (e = grow_host(hp.h_groups, hp.h_groups_cap, ng)) != hipSuccess ||
@@ -435,10 +439,14 @@ int ensure_field_plan(Workspace *ws, int64_t n, int64_t S, const int32_t *sx, co
     return map_err(e);
   std::copy(rows.begin(), rows.end(), hp.h_rows);
   std::copy(first.begin(), first.end(), hp.h_first);
+  std::fill(hp.h_row_of_y, hp.h_row_of_y + n, -1);
+  for (int64_t r = 0; r < nr; ++r) hp.h_row_of_y[rows[(size_t)r]] = (int)r;
   std::copy(groups.begin(), groups.end(), hp.h_groups);
   for (int64_t i = 0; i < S; ++i)
     hp.h_lines[i] = make_int2(order[(size_t)i], sx[order[(size_t)i]]);
-  if ((e = hipMemcpyAsync(hp.d_first, hp.h_first, sizeof(int) * (size_t)(nr + 1),
+  if ((e = hipMemcpyAsync(hp.d_row_of_y, hp.h_row_of_y, sizeof(int) * (size_t)n,
+                          hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(hp.d_first, hp.h_first, sizeof(int) * (size_t)(nr + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
       (nr > 0 && (e = hipMemcpyAsync(hp.d_rows, hp.h_rows, sizeof(int) * (size_t)nr,
                                      hipMemcpyHostToDevice, ws->stream)) != hipSuccess) ||
@@ -740,7 +748,8 @@ int lyaf_field_skewers(const lyaf_field_params *fp, const void *modes, const dou
   if ((rc = ensure_twiddles(ws, st))) return rc;
   const int64_t H = N / 2 + 1;
   hipError_t e;
-  if ((e = field_kernel_attributes()) != hipSuccess ||
+  int ky_resident = 0;
+  if ((e = field_kernel_attributes(&ky_resident)) != hipSuccess ||
       (e = grow_dev(ws->field_T, ws->field_T_cap, 2 * (int64_t)hp->n_rows * N * H)) !=
           hipSuccess ||
       (e = grow_dev(ws->field_C, ws->field_C_cap, 2 * n_lines * H)) != hipSuccess)
@@ -769,7 +778,8 @@ int lyaf_field_skewers(const lyaf_field_params *fp, const void *modes, const dou
   a.delta_b = delta_b;
   a.v_z = v_z;
   a.twiddle = ws->ps_twiddle;
-  if ((e = timed("field_ky", st, [&] { return launch_field_ky(a, st); })) != hipSuccess ||
+  if ((e = timed("field_ky", st, [&] { return launch_field_ky(a, ky_resident, st); })) !=
+          hipSuccess ||
       (e = timed("field_kx", st, [&] { return launch_field_kx(a, hp->n_groups, st); })) !=
           hipSuccess)
     return map_err(e);
@@ -807,9 +817,14 @@ int lyaf_flux_power_3d(const lyaf_power3d_params *pp, int64_t n_lines, const flo
   const int C = p3d_y_columns((int)n);
   y_grid = (int)std::min<int64_t>(y_grid, n * ((H + C - 1) / C));
   const int64_t n_c = n_lines * H + n * (int64_t)hp->n_rows * H;  // G, D1
-  const int64_t n_r = H + n * n + (int64_t)y_grid * 4 * nb;      // P1d, P2d, shells
+  const int64_t p1d_parts = (n_lines + kP3dP1dChunk - 1) / kP3dP1dChunk;
+  // P1d, P2d, data shells, geometry shells, P1d partials
+  const int64_t n_r = H + n * n + 2 * ((int64_t)y_grid * 2 * nb) + p1d_parts * H;
+  const bool need_geom = ws->p3d_geom_n != (int)n || ws->p3d_geom_nb != nb;
+  if (need_geom) ws->p3d_geom_n = ws->p3d_geom_nb = 0;
   if ((e = grow_dev(ws->p3d_c, ws->p3d_c_cap, n_c)) != hipSuccess ||
-      (e = grow_dev(ws->p3d_r, ws->p3d_r_cap, n_r)) != hipSuccess)
+      (e = grow_dev(ws->p3d_r, ws->p3d_r_cap, n_r)) != hipSuccess ||
+      (e = grow_dev(ws->p3d_geom, ws->p3d_geom_cap, 2 * (int64_t)nb)) != hipSuccess)
     return map_err(e);
   P3dArgs a;
   a.F = F;
@@ -830,12 +845,21 @@ int lyaf_flux_power_3d(const lyaf_power3d_params *pp, int64_t n_lines, const flo
   a.P1d = ws->p3d_r;
   a.P2d = ws->p3d_r + H;
   a.shells = ws->p3d_r + H + n * n;
+  a.geom_part = a.shells + (int64_t)y_grid * 2 * nb;
+  a.p1d_part = a.geom_part + (int64_t)y_grid * 2 * nb;
+  a.geom = ws->p3d_geom;
+  a.row_of_y = hp->d_row_of_y;
   a.counts = counts;
   a.k_mean = k_mean;
   a.p_true = p_true;
   a.p_box = p_box;
   a.twiddle = ws->ps_twiddle;
-  return map_err(timed("flux_power_3d", st, [&] { return launch_power3d(a, y_grid, st); }));
+  if ((e = timed("flux_power_3d", st,
+                 [&] { return launch_power3d(a, y_grid, need_geom, st); })) != hipSuccess)
+    return map_err(e);
+  ws->p3d_geom_n = (int)n;
+  ws->p3d_geom_nb = nb;
+  return LYAF_OK;
 }
 
 double lyaf_angstrom_to_kms(double dlambda_angstrom, double z) {

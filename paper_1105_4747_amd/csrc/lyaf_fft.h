@@ -44,6 +44,19 @@ __device__ inline float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
 __device__ inline double2 conj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ inline float2 conj(float2 a) { return make_float2(a.x, -a.y); }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations (lgkmcnt(0); vmcnt and expcnt left at their maxima, encoding
+// 0xC07F on gfx9-family parts), then s_barrier.  Unlike __syncthreads() it
+// does not wait for global loads, so reads of the next tile issued before it
+// stay in flight across the transform's passes.  The empty asm statements keep
+// the compiler from moving memory accesses across it.
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <typename V>
 __device__ inline V twiddle_as(double2 w);
 template <>
@@ -120,8 +133,11 @@ __device__ void fft_pass(V *buf, const double2 *__restrict__ T, int N, int lgC, 
         y[b][1] = csub(x[0], a1);
       }
     }
+    // one butterfly's inputs live at a time: without this the compiler reads
+    // every butterfly's inputs first and runs out of registers at large B
+    asm volatile("" ::: "memory");
   }
-  __syncthreads();  // every read of this pass is done
+  lds_barrier();  // every read of this pass is done
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int q = (int)threadIdx.x + b * THREADS;
@@ -134,11 +150,12 @@ __device__ void fft_pass(V *buf, const double2 *__restrict__ T, int N, int lgC, 
       for (int r = 0; r < R; ++r) buf[((base + r * Ns) << lgC) + c] = y[b][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // The whole forward transform of the batch (N >= 1; N = 1 is the identity).
-// The caller has published buf with a barrier; the last pass ends with one.
+// The caller has published buf with a barrier; the last pass ends with one
+// (LDS only: global loads issued before the transform may still be in flight).
 template <int THREADS, int CAP, typename V>
 __device__ void fft_batch(V *buf, const double2 *__restrict__ T, int N, int lgC) {
   int Ns = 1;

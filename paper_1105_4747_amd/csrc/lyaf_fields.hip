@@ -16,7 +16,8 @@
 //   T(mx, y, mz) = sum_my e^{2 pi i my y / N} F(mx, my, mz).
 //
 // Three kernels, all reading their inputs once:
-//   field_ky_kernel  one workgroup per (mx, run of C consecutive mz): reads the
+//   field_ky_kernel  persistent workgroups over (mx, run of C consecutive mz)
+//                    items, the next item's modes read ahead: reads the
 //                    N x C modes (C consecutive mz are contiguous), forms both
 //                    fields' spectra (FP32 multipliers), inverse-transforms
 //                    the 2C columns along my in LDS as one batch (FP32,
@@ -40,7 +41,7 @@ namespace lyaf {
 namespace {
 
 constexpr int kKyThreads = 1024;
-constexpr int kKyCap = 16384;  // N C complex floats in LDS (128 KB)
+constexpr int kKyCap = 16384;  // N 2C complex floats in LDS (128 KB)
 constexpr int kKxThreads = 256;
 constexpr int kKxLines = kFieldLinesPerGroup;  // sight-lines per group
 constexpr int kZThreads = 256;
@@ -76,42 +77,75 @@ __device__ inline int xcd_item(int n_items) {
   return item < n_items ? item : -1;
 }
 
+// Persistent: workgroup b takes items b', b' + G, .. (G workgroups; b' puts
+// the workgroups of one XCD on consecutive items, whose mz runs share cache
+// lines), and reads the next item's modes into registers while the current
+// one is transformed and stored.
 __global__ __launch_bounds__(kKyThreads) void field_ky_kernel(FieldArgs a, int lgC,
                                                                int n_chunks) {
   // [N][2][C]: both fields' C columns side by side, one batch of 2C transforms
   extern __shared__ float2 lds_ky[];
-  const int item = xcd_item(a.N * n_chunks);
-  if (item < 0) return;
   const int N = a.N, H = a.H;
   const int C = 1 << lgC;
-  const int kx = item / n_chunks;
-  const int kz0 = (item - kx * n_chunks) * C;
-  const int mx = kx <= N / 2 ? kx : kx - N;
+  const int n_items = N * n_chunks;
   const int n_el = N << lgC;
-  const float2 *src = a.modes + (size_t)kx * N * H + kz0;
-  for (int q = threadIdx.x; q < n_el; q += kKyThreads) {
-    const int ky = q >> lgC, c = q & (C - 1);
-    float2 b = make_float2(0.f, 0.f), v = make_float2(0.f, 0.f);
-    if (kz0 + c < H) {
-      const float2 g = src[(size_t)ky * H + c];
-      float fb, fv;
-      field_factors(a, mx, ky <= N / 2 ? ky : ky - N, kz0 + c, fb, fv);
-      // conjugated on the way in: the inverse transform is conj(FFT(conj))
-      b = make_float2(g.x * fb, -g.y * fb);
-      v = make_float2(-g.y * fv, -g.x * fv);  // conj(i fv g)
+  const int G = (int)gridDim.x;  // a multiple of 8
+  const int first = ((int)blockIdx.x & 7) * (G >> 3) + ((int)blockIdx.x >> 3);
+  constexpr int E = kKyCap / 2 / kKyThreads;  // modes per thread per item
+  float2 nxt[E];
+  auto fetch = [&](int item) {
+    const int kx = item / n_chunks;
+    const int kz0 = (item - kx * n_chunks) * C;
+    const float2 *src = a.modes + (size_t)kx * N * H + kz0;
+    int tx = (int)threadIdx.x;
+    asm volatile("" : "+v"(tx));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = tx + e * kKyThreads;
+      nxt[e] = make_float2(0.f, 0.f);
+      if (q < n_el && kz0 + (q & (C - 1)) < H) nxt[e] = src[(size_t)(q >> lgC) * H + (q & (C - 1))];
     }
-    lds_ky[(ky << (lgC + 1)) + c] = b;
-    lds_ky[(ky << (lgC + 1)) + C + c] = v;
-  }
-  __syncthreads();
-  fft_batch<kKyThreads, kKyCap>(lds_ky, a.twiddle, N, lgC + 1);
-  const int n_out = a.n_rows << (lgC + 1);
-  for (int q = threadIdx.x; q < n_out; q += kKyThreads) {
-    const int yi = q >> (lgC + 1), f = (q >> lgC) & 1, c = q & (C - 1);
-    if (kz0 + c < H) {
-      float2 *dst = (f == 0 ? a.Tb : a.Tv) + ((size_t)yi * N + kx) * H + kz0 + c;
-      *dst = conj(lds_ky[(a.rows[yi] << (lgC + 1)) + (f << lgC) + c]);
+  };
+  if (first < n_items) fetch(first);
+  for (int item = first; item < n_items; item += G) {
+    const int kx = item / n_chunks;
+    const int kz0 = (item - kx * n_chunks) * C;
+    const int mx = kx <= N / 2 ? kx : kx - N;
+    // the per-element indices below are recomputed for every item: hoisted out
+    // of the item loop they would hold E sets of registers for its whole length
+    int tx = (int)threadIdx.x;
+    asm volatile("" : "+v"(tx));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = tx + e * kKyThreads;
+      if (q < n_el) {
+        const int ky = q >> lgC, c = q & (C - 1);
+        float2 b = make_float2(0.f, 0.f), v = make_float2(0.f, 0.f);
+        if (kz0 + c < H) {
+          const float2 g = nxt[e];
+          float fb, fv;
+          field_factors(a, mx, ky <= N / 2 ? ky : ky - N, kz0 + c, fb, fv);
+          // conjugated on the way in: the inverse transform is conj(FFT(conj))
+          b = make_float2(g.x * fb, -g.y * fb);
+          v = make_float2(-g.y * fv, -g.x * fv);  // conj(i fv g)
+        }
+        lds_ky[(ky << (lgC + 1)) + c] = b;
+        lds_ky[(ky << (lgC + 1)) + C + c] = v;
+      }
+      asm volatile("" ::: "memory");  // one element's multipliers at a time
     }
+    lds_barrier();
+    if (item + G < n_items) fetch(item + G);  // in flight during the transform
+    fft_batch<kKyThreads, kKyCap>(lds_ky, a.twiddle, N, lgC + 1);
+    const int n_out = a.n_rows << (lgC + 1);
+    for (int q = threadIdx.x; q < n_out; q += kKyThreads) {
+      const int yi = q >> (lgC + 1), f = (q >> lgC) & 1, c = q & (C - 1);
+      if (kz0 + c < H) {
+        float2 *dst = (f == 0 ? a.Tb : a.Tv) + ((size_t)yi * N + kx) * H + kz0 + c;
+        *dst = conj(lds_ky[(a.rows[yi] << (lgC + 1)) + (f << lgC) + c]);
+      }
+    }
+    lds_barrier();  // every read of the buffer is done before the next item
   }
 }
 
@@ -124,7 +158,7 @@ __device__ inline double2 root_of_unity(const double2 *__restrict__ T, int t, in
 }
 
 __global__ __launch_bounds__(kKxThreads) void field_kx_kernel(FieldArgs a, int n_kzb) {
-  __shared__ double2 tw[kFieldMaxN];
+  extern __shared__ double2 tw[];  // [N]
   const int g = (int)blockIdx.x / n_kzb;
   const int kzb = (int)blockIdx.x - g * n_kzb;
   const int N = a.N, H = a.H;
@@ -135,6 +169,7 @@ __global__ __launch_bounds__(kKxThreads) void field_kx_kernel(FieldArgs a, int n
   for (int m = 0; m < kKxLines; ++m) xs[m] = m < grp.z ? a.lines[grp.y + m].y : 0;
   __syncthreads();
   const int kz = kzb * kKxThreads + (int)threadIdx.x;
+  if (kz - (int)(threadIdx.x & 63) >= H) return;  // the wave holds no mz
   const bool valid = kz < H;
   const size_t base = (size_t)grp.x * N * H + (valid ? kz : 0);
   const float2 *rb = a.Tb + base;
@@ -222,11 +257,17 @@ bool g_attr_set[64] = {false};
 
 int field_ky_columns(int N) { return std::min(16, kKyCap / (2 * N)); }
 
-hipError_t field_kernel_attributes() {
+int g_ky_resident[64] = {0};
+
+hipError_t field_kernel_attributes(int *ky_resident) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= 64 || g_attr_set[dev]) return hipSuccess;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (g_attr_set[dev]) {
+    *ky_resident = g_ky_resident[dev];
+    return hipSuccess;
+  }
   if ((e = hipFuncSetAttribute((const void *)field_ky_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(sizeof(float2) * kKyCap))) != hipSuccess)
@@ -235,17 +276,27 @@ hipError_t field_kernel_attributes() {
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(sizeof(double2) * kFieldMaxN))) != hipSuccess)
     return e;
+  int per_cu = 0, cus = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)field_ky_kernel,
+                                                        kKyThreads,
+                                                        sizeof(float2) * kKyCap)) != hipSuccess ||
+      (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+          hipSuccess)
+    return e;
+  g_ky_resident[dev] = std::max(1, per_cu) * cus;
   g_attr_set[dev] = true;
+  *ky_resident = g_ky_resident[dev];
   return hipSuccess;
 }
 
-hipError_t launch_field_ky(const FieldArgs &a, hipStream_t st) {
+hipError_t launch_field_ky(const FieldArgs &a, int resident, hipStream_t st) {
   const int C = field_ky_columns(a.N);
   int lgC = 0;
   while ((1 << lgC) < C) ++lgC;
   const int n_chunks = (a.H + C - 1) / C;
   const int items = a.N * n_chunks;
-  const int grid = (items + 7) / 8 * 8;
+  // persistent: the resident workgroups, at most the items, a multiple of 8
+  const int grid = std::max(8, std::min(resident, (items + 7) / 8 * 8) / 8 * 8);
   hipLaunchKernelGGL(field_ky_kernel, dim3(grid), dim3(kKyThreads),
                      sizeof(float2) * (size_t)(a.N << (lgC + 1)), st, a, lgC, n_chunks);
   return hipGetLastError();
@@ -254,7 +305,8 @@ hipError_t launch_field_ky(const FieldArgs &a, hipStream_t st) {
 hipError_t launch_field_kx(const FieldArgs &a, int n_groups, hipStream_t st) {
   const int n_kzb = (a.H + kKxThreads - 1) / kKxThreads;
   if (n_groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(field_kx_kernel, dim3(n_groups * n_kzb), dim3(kKxThreads), 0, st, a,
+  hipLaunchKernelGGL(field_kx_kernel, dim3(n_groups * n_kzb), dim3(kKxThreads),
+                     sizeof(double2) * (size_t)a.N, st, a,
                      n_kzb);
   return hipGetLastError();
 }

@@ -86,6 +86,8 @@ struct Workspace {
   // 3D flux power: complex (G, D1) and real (P1d, P2d, shell partials) buffers
   double2 *p3d_c = nullptr;    int64_t p3d_c_cap = 0;
   double *p3d_r = nullptr;     int64_t p3d_r_cap = 0;
+  double *p3d_geom = nullptr;  int64_t p3d_geom_cap = 0;  // shells' counts and |m| sums
+  int p3d_geom_n = 0, p3d_geom_nb = 0;                    // grid they belong to (0: none)
 };
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
@@ -192,14 +194,17 @@ struct FieldArgs {
   const double2 *twiddle;  // the shared FFT table (kFftTableLen / 2 entries)
 };
 int field_ky_columns(int N);  // mz values per field_ky work item
-hipError_t field_kernel_attributes();
-hipError_t launch_field_ky(const FieldArgs &a, hipStream_t st);
+// Sets the kernels' LDS limits once per device; *ky_resident: resident
+// workgroups of the persistent my-transform kernel.
+hipError_t field_kernel_attributes(int *ky_resident);
+hipError_t launch_field_ky(const FieldArgs &a, int resident, hipStream_t st);
 hipError_t launch_field_kx(const FieldArgs &a, int n_groups, hipStream_t st);
 hipError_t launch_field_z(const FieldArgs &a, int n_lines, hipStream_t st);
 constexpr int kFieldLinesPerGroup = 8;
 // 3D flux power spectrum of eq. (7) from sight-lines.
 constexpr int kP3dMaxN = 2048;        // pixels per sight-line = grid side
 constexpr int kP3dMaxLds = 160 * 1024;  // LDS of one workgroup
+constexpr int kP3dP1dChunk = 256;       // sight-lines per partial sum of P_1D
 struct P3dArgs {
   const float *F;         // device [S][n] flux
   const double *w;        // device [S] weights or null (all 1)
@@ -208,13 +213,17 @@ struct P3dArgs {
   double inv_mean;        // 1 / Fbar
   double L, p_noise;      // box side, flat 1D noise power
   const int *rows;        // device [n_rows]: y of each row in use
+  const int *row_of_y;    // device [n]: row index of y, -1 for rows without sight-lines
   const int *row_first;   // device [n_rows + 1]: the row's sight-lines in `lines`
   const int2 *lines;      // device [S]: (sight-line, x), grouped by row
   double2 *G;             // device [S][H]: the sight-lines' transforms
   double *P1d;            // device [H]
+  double *p1d_part;       // device [ceil(S / 256)][H] partial sums of P_1D
   double *P2d;            // device [n][n] (mx, my)
   double2 *D1;            // device [n][n_rows][H]: sum over a row's sight-lines
-  double *shells;         // device [workgroups][4][shells]
+  double *shells;         // device [workgroups][2][shells]: P_true, P_box sums
+  double *geom_part;      // device [workgroups][2][shells]: counts, |m| sums
+  double *geom;           // device [2][shells], kept across calls
   double *counts, *k_mean, *p_true, *p_box;  // device [n_bins] outputs
   const double2 *twiddle;  // the shared FFT table
 };
@@ -223,7 +232,8 @@ int p3d_y_columns(int n);               // mz per item of the y transform
 // Sets the kernels' LDS limits once per device; *y_grid: resident workgroups
 // of the y-transform kernel for grid side n and nb shells.
 hipError_t p3d_kernel_attributes(int n, int nb, int *y_grid);
-hipError_t launch_power3d(const P3dArgs &a, int y_grid, hipStream_t st);
+// need_geom: (re)compute the shells' counts and |m| sums into a.geom first.
+hipError_t launch_power3d(const P3dArgs &a, int y_grid, bool need_geom, hipStream_t st);
 hipError_t launch_tau_adjoint(const Batch &b, const int2 *items, int64_t n_items,
                               const int64_t *item_base_dev, const float *g,
                               float *gdelta, float *gvpec, double *gT0,

@@ -20,7 +20,8 @@
 //   p3d_line_kernel  one workgroup per sight-line: G_s by a half-length
 //                    complex transform in LDS and the unpacking of the two
 //                    real halves (as the 1D flux power);
-//   p3d_p1d_kernel   P_1D(mz), a fixed-order sum over the sight-lines;
+//   p3d_p1d_kernel   P_1D(mz), fixed-order sums over chunks of sight-lines,
+//                    then over the chunks (p3d_p1d_sum_kernel);
 //   p3d_w_kernel     one workgroup per mx: the rows' weight sums
 //                    sum_{s in row y} w_s e^{-2 pi i mx x_s / n}, placed in
 //                    their rows, transformed along y: P_2D,w(mx, .);
@@ -29,11 +30,17 @@
 //                    for every mx (a direct sum over the row's few sight-lines);
 //   p3d_y_kernel     persistent workgroups over (mx, run of C mz) items: the
 //                    rows of D1 placed in an LDS column per mz (zeros in rows
-//                    without sight-lines), transformed along y, then every
-//                    mode's P_box and P_true added into LDS shell sums with
-//                    FP64 atomics; each workgroup writes its shells once;
+//                    without sight-lines; the next item's rows read into
+//                    registers meanwhile), transformed along y, then every
+//                    mode's weighted P_box and P_true added into LDS shell
+//                    sums with FP64 atomics; each workgroup writes its shells
+//                    once.  The shells' mode counts and sums of |m| depend on
+//                    the grid alone: the same kernel computes them without
+//                    data once per grid and shell count, and the workspace
+//                    keeps them;
 //   p3d_bin_kernel   the shells of every workgroup summed in a fixed order,
-//                    then the means.
+//                    then the means (p3d_geom_sum_kernel likewise for the
+//                    counts).
 // Only the LDS atomics make the shell sums' order vary from run to run (the
 // results agree to rounding, not bitwise).
 #include <algorithm>
@@ -50,6 +57,7 @@ constexpr int kXLines = 8;       // a row's sight-lines held in registers at onc
 constexpr int kYThreads = 1024;
 constexpr int kYCap = 8192;      // n C complex doubles in LDS (128 KB)
 constexpr int kBinThreads = 256;
+constexpr int kP1dChunk = kP3dP1dChunk;
 
 // e^{-2 pi i t / n} for 0 <= t < n from the half-period table.
 __device__ inline double2 root_fwd(const double2 *__restrict__ T, int t, int n) {
@@ -94,15 +102,34 @@ __global__ __launch_bounds__(kLineThreads) void p3d_line_kernel(P3dArgs a) {
   }
 }
 
-// P_1D(mz) = L n^-2 (1/S) sum_s |G_s(mz)|^2, summed over s in order.
-__global__ __launch_bounds__(256) void p3d_p1d_kernel(P3dArgs a) {
+// P_1D(mz) = L n^-2 (1/S) sum_s |G_s(mz)|^2 in two fixed-order stages:
+// workgroup (mz block of 64, chunk of kP1dChunk sight-lines) sums its chunk
+// (each wave a strided quarter of it, then the four waves in order) into
+// part[chunk][mz]; p3d_p1d_sum_kernel adds the chunks in order.
+__global__ __launch_bounds__(256) void p3d_p1d_kernel(P3dArgs a, int n_kzb) {
+  __shared__ double sh[256];
+  const int kzb = (int)blockIdx.x % n_kzb, chunk = (int)blockIdx.x / n_kzb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kz = kzb * 64 + lane;
+  const int s_end = min(a.n_lines, (chunk + 1) * kP1dChunk);
+  double acc = 0.0;
+  if (kz < a.H)
+    for (int s = chunk * kP1dChunk + wave; s < s_end; s += 4) {
+      const double2 g = a.G[(size_t)s * a.H + kz];
+      acc = __builtin_fma(g.x, g.x, __builtin_fma(g.y, g.y, acc));
+    }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if (wave == 0 && kz < a.H)
+    a.p1d_part[(size_t)chunk * a.H + kz] = ((sh[lane] + sh[64 + lane]) + sh[128 + lane]) +
+                                           sh[192 + lane];
+}
+
+__global__ __launch_bounds__(256) void p3d_p1d_sum_kernel(P3dArgs a, int n_chunks) {
   const int kz = blockIdx.x * 256 + threadIdx.x;
   if (kz >= a.H) return;
   double acc = 0.0;
-  for (int s = 0; s < a.n_lines; ++s) {
-    const double2 g = a.G[(size_t)s * a.H + kz];
-    acc = __builtin_fma(g.x, g.x, __builtin_fma(g.y, g.y, acc));
-  }
+  for (int c = 0; c < n_chunks; ++c) acc += a.p1d_part[(size_t)c * a.H + kz];
   const double n = (double)a.n;
   a.P1d[kz] = a.L / (n * n) * acc / (double)a.n_lines;
 }
@@ -187,73 +214,129 @@ __global__ __launch_bounds__(kXThreads) void p3d_x_kernel(P3dArgs a, int n_kzb) 
   }
 }
 
-// The transform along y of (mx, run of C mz) items, and the shell sums.
+// Shell index and weight of mode (mx, my, mz) on the half-spectrum.
+__device__ inline int shell_of(int mx, int my, int mz, int n, double &m, double &wt) {
+  m = sqrt((double)(mx * mx + my * my + mz * mz));
+  wt = (mz == 0 || mz == n / 2) ? 1.0 : 2.0;
+  return (int)m;  // floor: m >= 0
+}
+
+// The transform along y of (mx, run of C mz) items, and the shell sums of
+// P_true and P_box.  Each workgroup loops over items with the next item's rows
+// of D1 read into registers while the current one is transformed and binned
+// (the transform's barriers wait for LDS traffic only); every mode adds its two
+// weighted powers into LDS shell sums with FP64 atomics, and each workgroup
+// writes its shells once.  GEOM = true runs the same loop over the modes
+// without data: the shells' mode counts and sums of weighted |m|, which depend
+// only on the grid and are kept by the caller across calls.
+template <bool GEOM>
 __global__ __launch_bounds__(kYThreads) void p3d_y_kernel(P3dArgs a, int lgC, int n_chunks,
                                                           int nb) {
-  extern __shared__ double2 lds_y[];  // [n][C], then 4 nb shell sums
+  extern __shared__ double2 lds_y[];  // [n][C], then 2 nb shell sums
   const int n = a.n, H = a.H, C = 1 << lgC;
-  double *bins = reinterpret_cast<double *>(lds_y + (n << lgC));
-  for (int i = threadIdx.x; i < 4 * nb; i += kYThreads) bins[i] = 0.0;
+  double *bins = reinterpret_cast<double *>(lds_y + (GEOM ? 0 : (n << lgC)));
+  for (int i = threadIdx.x; i < 2 * nb; i += kYThreads) bins[i] = 0.0;
   const double nn = (double)n * (double)n;
   const double box_scale = a.L * a.L * a.L / (nn * nn * nn);
   const int n_items = n * n_chunks;
   const int n_el = n << lgC;
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  constexpr int E = kYCap / kYThreads;  // elements per thread
+  double2 nxt[E];
+  // element q = threadIdx.x + e kYThreads is (y = q >> lgC, column c = q & (C-1))
+  auto fetch = [&](int item) {
+    const int kx = item / n_chunks;
+    const int kz0 = (item - kx * n_chunks) * C;
+    const double2 *src = a.D1 + (size_t)kx * a.n_rows * H + kz0;
+    int tx = (int)threadIdx.x;
+    asm volatile("" : "+v"(tx));  // indices per item, not hoisted out of the loop
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = tx + e * kYThreads;
+      nxt[e] = make_double2(0.0, 0.0);
+      if (q < n_el) {
+        const int r = a.row_of_y[q >> lgC], c = q & (C - 1);
+        if (r >= 0 && kz0 + c < H) nxt[e] = src[(size_t)r * H + c];
+      }
+    }
+  };
+  int item = blockIdx.x;
+  if (!GEOM && item < n_items) fetch(item);
+  __syncthreads();  // the shell sums are cleared
+  for (; item < n_items; item += gridDim.x) {
     const int kx = item / n_chunks;
     const int kz0 = (item - kx * n_chunks) * C;
     const int mx = kx <= n / 2 ? kx : kx - n;
-    for (int q = threadIdx.x; q < n_el; q += kYThreads) lds_y[q] = make_double2(0.0, 0.0);
-    __syncthreads();
-    const int n_in = a.n_rows << lgC;
-    for (int q = threadIdx.x; q < n_in; q += kYThreads) {
-      const int r = q >> lgC, c = q & (C - 1);
-      if (kz0 + c < H)
-        lds_y[(a.rows[r] << lgC) + c] = a.D1[((size_t)kx * a.n_rows + r) * H + kz0 + c];
+    if (!GEOM) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int q = (int)threadIdx.x + e * kYThreads;
+        if (q < n_el) lds_y[q] = nxt[e];
+      }
+      lds_barrier();
+      if (item + (int)gridDim.x < n_items) fetch(item + gridDim.x);  // in flight meanwhile
+      fft_batch<kYThreads, kYCap>(lds_y, a.twiddle, n, lgC);
     }
-    __syncthreads();
-    fft_batch<kYThreads, kYCap>(lds_y, a.twiddle, n, lgC);
     for (int q = threadIdx.x; q < n_el; q += kYThreads) {
       const int ky = q >> lgC, c = q & (C - 1);
       const int kz = kz0 + c;
       if (kz >= H) continue;
       const int my = ky <= n / 2 ? ky : ky - n;
-      const double2 D = lds_y[q];
-      const double pbox = box_scale * __builtin_fma(D.x, D.x, D.y * D.y);
-      const double ptrue = pbox - (a.P1d[kz] + a.p_noise) * a.P2d[(size_t)kx * n + ky];
-      const int m2 = mx * mx + my * my + kz * kz;
-      const double m = sqrt((double)m2);
-      const int b = (int)m;  // floor: m >= 0
-      if (b < nb) {
-        const double wt = (kz == 0 || kz == n / 2) ? 1.0 : 2.0;
+      double m, wt;
+      const int b = shell_of(mx, my, kz, n, m, wt);
+      if (b >= nb) continue;
+      if (GEOM) {
         atomicAdd(&bins[b], wt);
         atomicAdd(&bins[nb + b], wt * m);
-        atomicAdd(&bins[2 * nb + b], wt * ptrue);
-        atomicAdd(&bins[3 * nb + b], wt * pbox);
+      } else {
+        const double2 D = lds_y[q];
+        const double pbox = box_scale * __builtin_fma(D.x, D.x, D.y * D.y);
+        const double ptrue = pbox - (a.P1d[kz] + a.p_noise) * a.P2d[(size_t)kx * n + ky];
+        atomicAdd(&bins[b], wt * ptrue);
+        atomicAdd(&bins[nb + b], wt * pbox);
       }
     }
-    __syncthreads();  // the next item clears the buffer
+    if (!GEOM) lds_barrier();  // the next item overwrites the buffer
   }
-  double *out = a.shells + (size_t)blockIdx.x * 4 * nb;
-  for (int i = threadIdx.x; i < 4 * nb; i += kYThreads) out[i] = bins[i];
+  __syncthreads();
+  double *out = (GEOM ? a.geom_part : a.shells) + (size_t)blockIdx.x * 2 * nb;
+  for (int i = threadIdx.x; i < 2 * nb; i += kYThreads) out[i] = bins[i];
+}
+
+// The shells' mode counts and sums of weighted |m|, summed over the
+// workgroups of the geometry pass in a fixed order.
+__global__ __launch_bounds__(kBinThreads) void p3d_geom_sum_kernel(P3dArgs a, int nb,
+                                                                   int n_parts) {
+  const int b = blockIdx.x * kBinThreads + threadIdx.x;
+  if (b >= nb) return;
+  double t0 = 0.0, t1 = 0.0;
+  for (int p = 0; p < n_parts; ++p) {
+    const double *s = a.geom_part + (size_t)p * 2 * nb;
+    t0 += s[b];
+    t1 += s[nb + b];
+  }
+  a.geom[b] = t0;
+  a.geom[nb + b] = t1;
 }
 
 // Sum the workgroups' shells in a fixed order; means per shell.
 __global__ __launch_bounds__(kBinThreads) void p3d_bin_kernel(P3dArgs a, int nb, int n_parts) {
   const int b = blockIdx.x * kBinThreads + threadIdx.x;
   if (b >= a.n_bins) return;
-  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  double cnt = 0.0, km = 0.0, pt = 0.0, pb = 0.0;
   if (b < nb) {
+    cnt = a.geom[b];
+    km = a.geom[nb + b];
     for (int p = 0; p < n_parts; ++p) {
-      const double *s = a.shells + (size_t)p * 4 * nb;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) t[q] += s[q * nb + b];
+      const double *s = a.shells + (size_t)p * 2 * nb;
+      pt += s[b];
+      pb += s[nb + b];
     }
   }
-  const bool any = t[0] > 0.0;
-  a.counts[b] = t[0];
-  a.k_mean[b] = any ? t[1] / t[0] * (2.0 * M_PI / a.L) : 0.0;
-  a.p_true[b] = any ? t[2] / t[0] : 0.0;
-  a.p_box[b] = any ? t[3] / t[0] : 0.0;
+  const bool any = cnt > 0.0;
+  a.counts[b] = cnt;
+  a.k_mean[b] = any ? km / cnt * (2.0 * M_PI / a.L) : 0.0;
+  a.p_true[b] = any ? pt / cnt : 0.0;
+  a.p_box[b] = any ? pb / cnt : 0.0;
 }
 
 bool g_attr_set[64] = {false};
@@ -271,7 +354,7 @@ int p3d_shell_bins(int n, int n_bins) {
 // n C complex doubles fit kYCap and, with the shell sums of the largest
 // shell count, the LDS of one workgroup.
 int p3d_y_columns(int n) {
-  const size_t bins = 4 * sizeof(double) * (size_t)p3d_shell_bins(n, INT32_MAX);
+  const size_t bins = 2 * sizeof(double) * (size_t)p3d_shell_bins(n, INT32_MAX);
   int C = 16;
   while (C > 1 && ((size_t)n * C > (size_t)kYCap ||
                    sizeof(double2) * (size_t)n * C + bins > (size_t)kP3dMaxLds))
@@ -285,7 +368,10 @@ hipError_t p3d_kernel_attributes(int n, int nb, int *y_grid) {
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
   if (!g_attr_set[dev]) {
-    if ((e = hipFuncSetAttribute((const void *)p3d_y_kernel,
+    if ((e = hipFuncSetAttribute((const void *)p3d_y_kernel<false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kP3dMaxLds)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)p3d_y_kernel<true>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kP3dMaxLds)) != hipSuccess)
       return e;
@@ -299,32 +385,42 @@ hipError_t p3d_kernel_attributes(int n, int nb, int *y_grid) {
     g_attr_set[dev] = true;
   }
   const int C = p3d_y_columns(n);
-  const size_t lds = sizeof(double2) * (size_t)n * C + 4 * sizeof(double) * (size_t)nb;
+  const size_t lds = sizeof(double2) * (size_t)n * C + 2 * sizeof(double) * (size_t)nb;
   int per_cu = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)p3d_y_kernel,
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)p3d_y_kernel<false>,
                                                         kYThreads, lds)) != hipSuccess)
     return e;
   *y_grid = std::max(1, per_cu) * g_resident[dev];
   return hipSuccess;
 }
 
-hipError_t launch_power3d(const P3dArgs &a, int y_grid, hipStream_t st) {
+hipError_t launch_power3d(const P3dArgs &a, int y_grid, bool need_geom, hipStream_t st) {
   const int n = a.n;
-  hipLaunchKernelGGL(p3d_line_kernel, dim3(a.n_lines), dim3(kLineThreads),
-                     sizeof(double2) * (size_t)(n / 2), st, a);
-  hipLaunchKernelGGL(p3d_p1d_kernel, dim3((a.H + 255) / 256), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(p3d_w_kernel, dim3(n), dim3(kLineThreads), sizeof(double2) * (size_t)n,
-                     st, a);
-  const int n_kzb = (a.H + 63) / 64;
-  hipLaunchKernelGGL(p3d_x_kernel, dim3(a.n_rows * n_kzb), dim3(kXThreads), 0, st, a, n_kzb);
   const int C = p3d_y_columns(n);
   int lgC = 0;
   while ((1 << lgC) < C) ++lgC;
   const int n_chunks = (a.H + C - 1) / C;
   const int nb = p3d_shell_bins(n, a.n_bins);
   const int grid = std::min(y_grid, n * n_chunks);
-  hipLaunchKernelGGL(p3d_y_kernel, dim3(grid), dim3(kYThreads),
-                     sizeof(double2) * (size_t)(n << lgC) + 4 * sizeof(double) * (size_t)nb,
+  if (need_geom) {  // once per grid and shell count: counts and mean |k|
+    hipLaunchKernelGGL(p3d_y_kernel<true>, dim3(grid), dim3(kYThreads),
+                       2 * sizeof(double) * (size_t)nb, st, a, lgC, n_chunks, nb);
+    hipLaunchKernelGGL(p3d_geom_sum_kernel, dim3((nb + kBinThreads - 1) / kBinThreads),
+                       dim3(kBinThreads), 0, st, a, nb, grid);
+  }
+  hipLaunchKernelGGL(p3d_line_kernel, dim3(a.n_lines), dim3(kLineThreads),
+                     sizeof(double2) * (size_t)(n / 2), st, a);
+  const int p1d_kzb = (a.H + 63) / 64;
+  const int p1d_chunks = (a.n_lines + kP1dChunk - 1) / kP1dChunk;
+  hipLaunchKernelGGL(p3d_p1d_kernel, dim3(p1d_kzb * p1d_chunks), dim3(256), 0, st, a, p1d_kzb);
+  hipLaunchKernelGGL(p3d_p1d_sum_kernel, dim3((a.H + 255) / 256), dim3(256), 0, st, a,
+                     p1d_chunks);
+  hipLaunchKernelGGL(p3d_w_kernel, dim3(n), dim3(kLineThreads), sizeof(double2) * (size_t)n,
+                     st, a);
+  const int n_kzb = (a.H + 63) / 64;
+  hipLaunchKernelGGL(p3d_x_kernel, dim3(a.n_rows * n_kzb), dim3(kXThreads), 0, st, a, n_kzb);
+  hipLaunchKernelGGL(p3d_y_kernel<false>, dim3(grid), dim3(kYThreads),
+                     sizeof(double2) * (size_t)(n << lgC) + 2 * sizeof(double) * (size_t)nb,
                      st, a, lgC, n_chunks, nb);
   hipLaunchKernelGGL(p3d_bin_kernel, dim3((a.n_bins + kBinThreads - 1) / kBinThreads),
                      dim3(kBinThreads), 0, st, a, nb, grid);
