@@ -80,8 +80,12 @@ extern "C" {
  * each lane owns 4 consecutive targets and walks its own run of sources, one
  * source stream per wave, 1024-pixel tiles; 1: the same with 512-pixel tiles;
  * 2: 8 source streams share 32-target sub-tiles, 4 targets per lane,
- * 512-pixel tiles; 3: as 2 with 2 targets per lane. */
-#define LYAF_NUM_SHAPES 4
+ * 512-pixel tiles; 3: as 2 with 2 targets per lane; 4: as 0 with the
+ * Gaussian of a source evaluated across the lane's 4 targets by a product
+ * recurrence (two exp2 per source and lane instead of four; a tile holding a
+ * line narrower than sqrt(log2 e) pixel widths, b < 1.2 dv, falls back to
+ * shape 0's arithmetic). */
+#define LYAF_NUM_SHAPES 5
 #define LYAF_FLAG_SHAPE(v) ((((uint32_t)(v)) + 1u) << 8)
 
 typedef struct lyaf_skewers {

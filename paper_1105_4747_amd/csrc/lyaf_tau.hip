@@ -519,7 +519,19 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-template <int NWAVES>
+// REC: the Gaussian recurrence across a lane's four targets.  With
+// t_k = t_0 + k a (a = dv r), t_k^2 - t_(k-1)^2 = a (2 t_(k-1) + a), so
+// E_k = exp2(-t_k^2) = E_(k-1) G_(k-1) with G_0 = exp2(-a (2 t_0 + a)) and
+// G_k = G_(k-1) C, C = exp2(-2 a^2) per source (staged in place of a, which is
+// then dv r): two exp2 per source and lane instead of four.  The chain starts
+// at the lane's first target; it is exact to rounding unless E_0 underflows
+// while a later E_k matters, which needs a > 1.16 (|t_0| > 11.2 and
+// |t_0 + 3a| < 7.75), so a tile with any source of a > kRecMaxA (unresolved
+// lines) takes the direct form.  G_0 is clamped at 2^64, reached only where
+// E_0 = 0 (t_0 < -32 for a <= 1), so that no product is 0 * inf.
+constexpr float kRecMaxA = 1.0f;
+
+template <int NWAVES, bool REC = false>
 __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
                                               float *__restrict__ tau, float4 *rec,
                                               int *gwin, const float4 *fdt) {
@@ -550,6 +562,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   const int cnt = (i_end - i0) + 2 * RH;
   const float pivot = b.pivot, wk = b.window_k;
   bool bad = false;
+  int unsafe = 0;  // REC: a source of a > kRecMaxA
   for (int c0 = 0; c0 < cnt; c0 += SIT * NT) {
     float dd[SIT], vv[SIT];
 #pragma unroll
@@ -578,7 +591,13 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
           flo = fminf(fmaxf(ceilf(cc - h), -8192.f), 8191.f);
           fhi = fminf(fmaxf(floorf(cc + h), -8192.f), 8191.f);
         }
-        rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], K.dv * o.r);
+        const float a = K.dv * o.r;
+        if (REC) {
+          unsafe |= (o.w > 0.f) && !(a <= kRecMaxA);
+          rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], fexp2(-2.f * a * a));
+        } else {
+          rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], a);
+        }
       }
       flo = stream_min<kSkewGroup>(flo);
       fhi = stream_max<kSkewGroup>(fhi);
@@ -588,7 +607,8 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     }
   }
   flag_bad_delta(b, bad);
-  __syncthreads();
+  const bool chain = REC ? __syncthreads_or(unsafe) == 0 : false;
+  if (!REC) __syncthreads();
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -634,21 +654,51 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     auto pair_step = [&](const float4 q, const float fd, const bool first) {
       const float d0 = __builtin_fmaf(fd, dv, -q.z);
       const float tt0 = d0 * q.y;
+      const float a = REC ? dv * q.y : q.w;  // REC records hold C in .w
 #pragma unroll
       for (int k = 0; k < kSkewM; ++k) {
-        const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, q.w, tt0);
+        const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, a, tt0);
         const float e = fexp2(-(t * t));
         acc[k] = first ? q.x * e : __builtin_fmaf(q.x, e, acc[k]);
       }
     };
+    // one source against the lane's kSkewM targets by the recurrence
+    auto pair_chain = [&](const float4 q, const float fd, const bool first) {
+      const float d0 = __builtin_fmaf(fd, dv, -q.z);
+      const float tt0 = d0 * q.y;
+      const float a = dv * q.y;
+      float E = fexp2(-(tt0 * tt0));
+      float G = fexp2(fminf(-(__builtin_fmaf(2.f, tt0, a) * a), 64.f));
+#pragma unroll
+      for (int k = 0; k < kSkewM; ++k) {
+        if (k > 0) {
+          E *= G;
+          if (k + 1 < kSkewM) G *= q.w;
+        }
+        acc[k] = first ? q.x * E : __builtin_fmaf(q.x, E, acc[k]);
+      }
+    };
     auto block = [&](const float4 (&q)[5], const bool first) {
+      if (REC && chain) {
+        pair_chain(q[0], q[4].x, first);
+        pair_chain(q[1], q[4].y, false);
+        pair_chain(q[2], q[4].z, false);
+        pair_chain(q[3], q[4].w, false);
+        // the block's 8 exps, one per seven other VALU instructions
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+          __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
+          __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);  // seven VALU
+        }
+        return;
+      }
       pair_step(q[0], q[4].x, first);
       pair_step(q[1], q[4].y, false);
       pair_step(q[2], q[4].z, false);
       pair_step(q[3], q[4].w, false);
-      // v_exp_f32 takes about two and a half VALU issue slots and does not
-      // overlap other VALU work of the wave: spread the block's 16 exps, one
-      // per four other VALU instructions
+      // v_exp_f32 takes about two VALU issue slots and does not overlap other
+      // VALU work of the wave: spread the block's 16 exps, one per four other
+      // VALU instructions
 #pragma unroll
       for (int z = 0; z < 4 * kSkewM; ++z) {
         __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
@@ -714,7 +764,7 @@ __device__ __forceinline__ void fill_offset_table(float4 *fdt) {
   }
 }
 
-template <int NWAVES>
+template <int NWAVES, bool REC>
 __global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
                                                                   const int2 *__restrict__ items,
                                                                   float *__restrict__ tau) {
@@ -722,12 +772,12 @@ __global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
   __shared__ int gwin[SkewShape<NWAVES>::kGroups];
   __shared__ float4 fdt[kFdN / 4];
   fill_offset_table(fdt);  // published by the barrier after staging
-  tau_skew_tile<NWAVES>(b, items[blockIdx.x], tau, rec, gwin, fdt);
+  tau_skew_tile<NWAVES, REC>(b, items[blockIdx.x], tau, rec, gwin, fdt);
 }
 
 // 4-wave form: at most 128 VGPRs, so that four waves share a SIMD as in the
 // grid form
-template <int NWAVES>
+template <int NWAVES, bool REC>
 __global__ __launch_bounds__(NWAVES * kWave)
 __attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
     Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
@@ -746,7 +796,7 @@ __attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persiste
     const int last = min(first + kQueueGrab, n_items);
     for (int idx = first; idx < last; ++idx) {
       if (idx > first) __syncthreads();  // the previous item is done with LDS
-      tau_skew_tile<NWAVES>(b, items[idx], tau, rec, gwin, fdt);
+      tau_skew_tile<NWAVES, REC>(b, items[idx], tau, rec, gwin, fdt);
     }
   }
 }
@@ -779,22 +829,22 @@ VariantFns make_variant() {
   return v;
 }
 
-template <int NWAVES>
+template <int NWAVES, bool REC = false>
 VariantFns make_skew_variant() {
   constexpr int NT = SkewShape<NWAVES>::kThreads;
   VariantFns v;
-  v.grid_fn = reinterpret_cast<const void *>(&tau_skew_kernel<NWAVES>);
-  v.pers_fn = reinterpret_cast<const void *>(&tau_skew_persistent_kernel<NWAVES>);
+  v.grid_fn = reinterpret_cast<const void *>(&tau_skew_kernel<NWAVES, REC>);
+  v.pers_fn = reinterpret_cast<const void *>(&tau_skew_persistent_kernel<NWAVES, REC>);
   v.threads = NT;
   v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
-    hipLaunchKernelGGL((tau_skew_kernel<NWAVES>), dim3((unsigned)n), dim3(NT), 0, st, b, items,
-                       tau);
+    hipLaunchKernelGGL((tau_skew_kernel<NWAVES, REC>), dim3((unsigned)n), dim3(NT), 0, st, b,
+                       items, tau);
   };
   v.pers = [](const Batch &b, const int2 *items, int64_t n, unsigned int *queue, int grid,
               float *tau, hipStream_t st) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, queue);
-    hipLaunchKernelGGL((tau_skew_persistent_kernel<NWAVES>), dim3((unsigned)grid), dim3(NT), 0,
-                       st, b, items, (int)n, queue, tau);
+    hipLaunchKernelGGL((tau_skew_persistent_kernel<NWAVES, REC>), dim3((unsigned)grid),
+                       dim3(NT), 0, st, b, items, (int)n, queue, tau);
   };
   return v;
 }
@@ -805,13 +855,15 @@ const VariantFns &variant_fns(int v) {
       make_skew_variant<2>(),
       make_variant<8, 4, 512>(),
       make_variant<8, 2, 512>(),
+      make_skew_variant<4, true>(),  // the Gaussian recurrence across a lane's targets
   };
   return table[v];
 }
 }  // namespace
 
 const TauVariant kTauVariants[kNumTauVariants] = {
-    {1, kSkewM, SkewShape<4>::kTile}, {1, kSkewM, SkewShape<2>::kTile}, {8, 4, 512}, {8, 2, 512}};
+    {1, kSkewM, SkewShape<4>::kTile}, {1, kSkewM, SkewShape<2>::kTile}, {8, 4, 512}, {8, 2, 512},
+    {1, kSkewM, SkewShape<4>::kTile}};
 
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items, float *tau,
                              hipStream_t st, int variant, int persistent_grid,
