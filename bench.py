@@ -438,13 +438,14 @@ def box_section(L, torch, dev, fields, timed, reps, peak):
 
 
 def tau_kernel_name(shape: int, persistent: bool) -> str:
-    """Kernel that LYAF_FLAG_SHAPE(shape) launches: shapes 0, 1 and 4 are the
-    skewed per-lane-run form (4 waves, 2 waves, 4 waves with the Gaussian
-    recurrence across a lane's targets), 2-3 the shared-run form with source
-    streams (as rocprofv3 names them)."""
+    """Kernel that LYAF_FLAG_SHAPE(shape) launches (as rocprofv3 names it):
+    shapes 0, 1, 4 and 5 are the skewed per-lane-run form (4 waves, 2 waves,
+    4 waves with the Gaussian recurrence across a lane's 4 targets, the same
+    across 8 targets), 2-3 the shared-run form with source streams."""
     suffix = "_persistent_kernel" if persistent else "_kernel"
-    return {0: "tau_skew%s<4, false>", 1: "tau_skew%s<2, false>", 2: "tau_window%s<8, 4, 512>",
-            3: "tau_window%s<8, 2, 512>", 4: "tau_skew%s<4, true>"}[shape] % suffix
+    return {0: "tau_skew%s<4, false, 4>", 1: "tau_skew%s<2, false, 4>", 2: "tau_window%s<8, 4, 512>",
+            3: "tau_window%s<8, 2, 512>", 4: "tau_skew%s<4, true, 4>",
+            5: "tau_skew%s<4, true, 8>"}[shape] % suffix
 
 
 def measured_traffic(shape: int, persistent: bool, workload: str):

@@ -119,7 +119,7 @@ hipError_t launch_reach(const Batch &b, hipStream_t st);
 struct TauVariant {
   int S, M, tile;
 };
-constexpr int kNumTauVariants = 5;
+constexpr int kNumTauVariants = 6;
 constexpr int kTauVariantDefault = 0;
 extern const TauVariant kTauVariants[kNumTauVariants];
 

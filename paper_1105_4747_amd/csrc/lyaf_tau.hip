@@ -494,20 +494,28 @@ constexpr int kSkewGroup = 4;              // sources per window-bounds group
 // Target-minus-source offsets as exact floats, read from LDS four at a time
 // (one broadcast read per block of four steps instead of a VALU decrement per
 // step): entry k holds kFdTop - k.  A lane run covers offsets H4 .. H4 - NS + 1
-// with H4 <= RH <= 476 and NS <= H4 + RH + 4, plus one block read ahead.
+// with H4 <= RH <= 476 and NS <= H4 + RH + M (M <= 8 targets per lane), plus
+// one block read ahead.
 constexpr int kSkewMaxRH = 476;  // staged margin limit of the windowed path
 constexpr int kFdTop = 480;
 constexpr int kFdN = 976;
-static_assert(kFdTop >= kSkewMaxRH + 4 && kFdN >= kFdTop + kSkewMaxRH + 8 && kFdN % 4 == 0,
+static_assert(kFdTop >= kSkewMaxRH + 4 && kFdN >= kFdTop + kSkewMaxRH + 12 && kFdN % 4 == 0,
               "offset table covers every lane run");
 
-template <int NWAVES>
+template <int NWAVES, int M = kSkewM>
 struct SkewShape {
+  static_assert(M == 4 || M == 8, "a lane owns 4 or 8 targets");
+  static constexpr int kLgM = M == 8 ? 3 : 2;
+  static constexpr int kSpan = kWave * M;  // targets per wave
   static constexpr int kThreads = NWAVES * kWave;
-  static constexpr int kTile = NWAVES * kSkewSpan;
-  // staged sources: tile + 2 RH with RH <= 476, so that five 4-wave
-  // workgroups fit in the 160 KiB of LDS of a compute unit
-  static constexpr int kChunkS = kTile + 952 > kChunk ? kTile + 952 : kChunk;
+  static constexpr int kTile = NWAVES * kSpan;
+  // staged sources: tile + 2 RH with RH <= kMaxRH, so that four 4-wave
+  // workgroups of 1024 targets fit in the 160 KiB of LDS of a compute unit
+  // (three of 2048 targets, whose margin is smaller: tiles reaching further
+  // take the full-sum path)
+  static constexpr int kMaxRH = M == 8 ? 252 : kSkewMaxRH;
+  static constexpr int kChunkS =
+      kTile + 2 * kMaxRH > kChunk ? kTile + 2 * kMaxRH : kChunk;
   static constexpr int kPlane = kChunkS / 4;
   static constexpr int kGroups = kChunkS / kSkewGroup;
   static_assert(kChunkS >= kChunk, "the full-sum path stages kChunk sources");
@@ -529,13 +537,16 @@ __device__ __forceinline__ int wave_max(int x) {
 // |t_0 + 3a| < 7.75), so a tile with any source of a > kRecMaxA (unresolved
 // lines) takes the direct form.  G_0 is clamped at 2^64, reached only where
 // E_0 = 0 (t_0 < -32 for a <= 1), so that no product is 0 * inf.
+// With 8 targets per lane the chain reaches 7a past its start: it is exact
+// unless a > 0.49 (|t_0| > 11.2 and |t_0 + 7a| < 7.75).
 constexpr float kRecMaxA = 1.0f;
+constexpr float kRecMaxA8 = 0.45f;
 
-template <int NWAVES, bool REC = false>
+template <int NWAVES, bool REC = false, int M = kSkewM>
 __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
                                               float *__restrict__ tau, float4 *rec,
                                               int *gwin, const float4 *fdt) {
-  using SH = SkewShape<NWAVES>;
+  using SH = SkewShape<NWAVES, M>;
   constexpr int TILE = SH::kTile, NT = SH::kThreads, PL = SH::kPlane;
   const int64_t s = item.x;
   const int i0 = item.y * TILE;
@@ -546,7 +557,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   // staged margin on each side, a multiple of 4 so that lane runs start on a
   // plane-0 column
   const int RH = (K.reach + kSkewMargin + 3) & ~3;
-  if (TILE + 2 * RH > SH::kChunkS || RH > kSkewMaxRH || 2 * RH + 8 > n) {
+  if (TILE + 2 * RH > SH::kChunkS || RH > SH::kMaxRH || 2 * RH + 8 > n) {
     // the window covers the box, or reaches beyond the staged margin
     for (int q = i0; q < i_end; q += NT) full_sum_tile<true>(b, K, off, q, tau, rec);
     return;
@@ -593,7 +604,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
         }
         const float a = K.dv * o.r;
         if (REC) {
-          unsafe |= (o.w > 0.f) && !(a <= kRecMaxA);
+          unsafe |= (o.w > 0.f) && !(a <= (M == 8 ? kRecMaxA8 : kRecMaxA));
           rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], fexp2(-2.f * a * a));
         } else {
           rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], a);
@@ -612,10 +623,10 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int t0 = i0 + wave * kSkewSpan;
+  const int t0 = i0 + wave * SH::kSpan;
   if (t0 >= i_end) return;
   const int T0r = t0 - e_lo;  // position of the wave's first target
-  const int last_lane = min(kWave - 1, (i_end - 1 - t0) >> 2);
+  const int last_lane = min(kWave - 1, (i_end - 1 - t0) >> SH::kLgM);
 
   // ---- H and NS for this wave, from the groups whose windows meet its
   // targets: the group's first position bounds (lane start - source) from
@@ -624,31 +635,33 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   {
     const int g_beg = (T0r - RH) / kSkewGroup;
     const int g_end = min((cnt + kSkewGroup - 1) / kSkewGroup,
-                          (T0r + kSkewSpan + RH + kSkewGroup - 1) / kSkewGroup);
+                          (T0r + SH::kSpan + RH + kSkewGroup - 1) / kSkewGroup);
     for (int g = g_beg + lane; g < g_end; g += kWave) {
       const int x = gwin[g];
       const int fh = (int)(int16_t)(x & 0xFFFF) - T0r;  // floor(hi) - T0r
-      const int fl = (x >> 16) - (kSkewM - 1) - T0r;
-      const int lhi = min(fh >> 2, last_lane);  // last lane whose targets the windows meet
-      const int llo = max((fl + 3) >> 2, 0);    // first such lane
+      const int fl = (x >> 16) - (M - 1) - T0r;
+      const int lhi = min(fh >> SH::kLgM, last_lane);  // last lane whose targets the windows meet
+      const int llo = max((fl + M - 1) >> SH::kLgM, 0);  // first such lane
       if (llo <= lhi) {
-        Hm = max(Hm, T0r + 4 * lhi - kSkewGroup * g);
-        Em = max(Em, kSkewGroup * g + kSkewGroup - 1 - T0r - 4 * llo);
+        Hm = max(Hm, T0r + M * lhi - kSkewGroup * g);
+        Em = max(Em, kSkewGroup * g + kSkewGroup - 1 - T0r - M * llo);
       }
     }
     Hm = __builtin_amdgcn_readfirstlane(wave_max(Hm));
     Em = __builtin_amdgcn_readfirstlane(wave_max(Em));
   }
   const int H4 = min((Hm + 3) & ~3, RH);
-  const int NS = min((H4 + Em + 1 + 3) & ~3, H4 + RH + 4);
-  const int i_l = t0 + kSkewM * lane;
+  // a lane's sources reach RH past its last target: the run never needs more
+  // than H4 + RH + M steps, which keeps every lane inside the staged range
+  const int NS = min((H4 + Em + 1 + 3) & ~3, H4 + RH + M);
+  const int i_l = t0 + M * lane;
 
-  float sum[kSkewM], comp[kSkewM];
+  float sum[M], comp[M];
 #pragma unroll
-  for (int k = 0; k < kSkewM; ++k) sum[k] = comp[k] = 0.f;
+  for (int k = 0; k < M; ++k) sum[k] = comp[k] = 0.f;
   if (Em >= -(1 << 19) && NS > 0) {
     const float dv = K.dv;
-    float acc[kSkewM];
+    float acc[M];
     // one source against the lane's kSkewM targets; fd is the exact target
     // minus source offset of the step; FIRST starts a new run
     auto pair_step = [&](const float4 q, const float fd, const bool first) {
@@ -656,7 +669,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       const float tt0 = d0 * q.y;
       const float a = REC ? dv * q.y : q.w;  // REC records hold C in .w
 #pragma unroll
-      for (int k = 0; k < kSkewM; ++k) {
+      for (int k = 0; k < M; ++k) {
         const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, a, tt0);
         const float e = fexp2(-(t * t));
         acc[k] = first ? q.x * e : __builtin_fmaf(q.x, e, acc[k]);
@@ -670,10 +683,10 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       float E = fexp2(-(tt0 * tt0));
       float G = fexp2(fminf(-(__builtin_fmaf(2.f, tt0, a) * a), 64.f));
 #pragma unroll
-      for (int k = 0; k < kSkewM; ++k) {
+      for (int k = 0; k < M; ++k) {
         if (k > 0) {
           E *= G;
-          if (k + 1 < kSkewM) G *= q.w;
+          if (k + 1 < M) G *= q.w;
         }
         acc[k] = first ? q.x * E : __builtin_fmaf(q.x, E, acc[k]);
       }
@@ -684,11 +697,12 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
         pair_chain(q[1], q[4].y, false);
         pair_chain(q[2], q[4].z, false);
         pair_chain(q[3], q[4].w, false);
-        // the block's 8 exps, one per seven other VALU instructions
+        // the block's 8 exps, one per 7 (M = 4) or 14 (M = 8) other VALU
+        // instructions
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
-          __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
-          __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);  // seven VALU
+          __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);            // one transcendental
+          __builtin_amdgcn_sched_group_barrier(0x002, M == 8 ? 14 : 7, 0);  // VALU
         }
         return;
       }
@@ -700,14 +714,14 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       // VALU work of the wave: spread the block's 16 exps, one per four other
       // VALU instructions
 #pragma unroll
-      for (int z = 0; z < 4 * kSkewM; ++z) {
+      for (int z = 0; z < 4 * M; ++z) {
         __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
         __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // four VALU
       }
     };
     auto fold = [&]() {
 #pragma unroll
-      for (int k = 0; k < kSkewM; ++k) {
+      for (int k = 0; k < M; ++k) {
         const float y = acc[k] - comp[k];
         const float tt = sum[k] + y;
         comp[k] = (tt - sum[k]) - y;
@@ -716,7 +730,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     };
     // column of the run's first source in every plane; a block is 4 steps
     // (one record from each plane), a run of kSkewFold steps is 4 blocks
-    const float4 *p = rec + ((T0r - H4) >> 2) + lane;
+    const float4 *p = rec + ((T0r - H4) >> 2) + lane * (M / 4);
     const float4 *pf = fdt + ((kFdTop - H4) >> 2);  // offsets H4 - 4 blk - (0..3)
     auto load = [&](float4 (&q)[5], const int blk) {
       q[0] = p[blk];
@@ -751,7 +765,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     }
   }
 #pragma unroll
-  for (int k = 0; k < kSkewM; ++k) {
+  for (int k = 0; k < M; ++k) {
     const int i = i_l + k;
     if (i < i_end) tau[off + i] = sum[k] - comp[k];
   }
@@ -764,26 +778,26 @@ __device__ __forceinline__ void fill_offset_table(float4 *fdt) {
   }
 }
 
-template <int NWAVES, bool REC>
+template <int NWAVES, bool REC, int M>
 __global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
                                                                   const int2 *__restrict__ items,
                                                                   float *__restrict__ tau) {
-  __shared__ float4 rec[SkewShape<NWAVES>::kChunkS + 4];
-  __shared__ int gwin[SkewShape<NWAVES>::kGroups];
+  __shared__ float4 rec[SkewShape<NWAVES, M>::kChunkS + 4];
+  __shared__ int gwin[SkewShape<NWAVES, M>::kGroups];
   __shared__ float4 fdt[kFdN / 4];
   fill_offset_table(fdt);  // published by the barrier after staging
-  tau_skew_tile<NWAVES, REC>(b, items[blockIdx.x], tau, rec, gwin, fdt);
+  tau_skew_tile<NWAVES, REC, M>(b, items[blockIdx.x], tau, rec, gwin, fdt);
 }
 
 // 4-wave form: at most 128 VGPRs, so that four waves share a SIMD as in the
 // grid form
-template <int NWAVES, bool REC>
+template <int NWAVES, bool REC, int M>
 __global__ __launch_bounds__(NWAVES * kWave)
 __attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
     Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
     float *__restrict__ tau) {
-  __shared__ float4 rec[SkewShape<NWAVES>::kChunkS + 4];
-  __shared__ int gwin[SkewShape<NWAVES>::kGroups];
+  __shared__ float4 rec[SkewShape<NWAVES, M>::kChunkS + 4];
+  __shared__ int gwin[SkewShape<NWAVES, M>::kGroups];
   __shared__ float4 fdt[kFdN / 4];
   __shared__ int next;
   fill_offset_table(fdt);
@@ -796,7 +810,7 @@ __attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persiste
     const int last = min(first + kQueueGrab, n_items);
     for (int idx = first; idx < last; ++idx) {
       if (idx > first) __syncthreads();  // the previous item is done with LDS
-      tau_skew_tile<NWAVES, REC>(b, items[idx], tau, rec, gwin, fdt);
+      tau_skew_tile<NWAVES, REC, M>(b, items[idx], tau, rec, gwin, fdt);
     }
   }
 }
@@ -829,21 +843,21 @@ VariantFns make_variant() {
   return v;
 }
 
-template <int NWAVES, bool REC = false>
+template <int NWAVES, bool REC = false, int M = kSkewM>
 VariantFns make_skew_variant() {
-  constexpr int NT = SkewShape<NWAVES>::kThreads;
+  constexpr int NT = SkewShape<NWAVES, M>::kThreads;
   VariantFns v;
-  v.grid_fn = reinterpret_cast<const void *>(&tau_skew_kernel<NWAVES, REC>);
-  v.pers_fn = reinterpret_cast<const void *>(&tau_skew_persistent_kernel<NWAVES, REC>);
+  v.grid_fn = reinterpret_cast<const void *>(&tau_skew_kernel<NWAVES, REC, M>);
+  v.pers_fn = reinterpret_cast<const void *>(&tau_skew_persistent_kernel<NWAVES, REC, M>);
   v.threads = NT;
   v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
-    hipLaunchKernelGGL((tau_skew_kernel<NWAVES, REC>), dim3((unsigned)n), dim3(NT), 0, st, b,
+    hipLaunchKernelGGL((tau_skew_kernel<NWAVES, REC, M>), dim3((unsigned)n), dim3(NT), 0, st, b,
                        items, tau);
   };
   v.pers = [](const Batch &b, const int2 *items, int64_t n, unsigned int *queue, int grid,
               float *tau, hipStream_t st) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, queue);
-    hipLaunchKernelGGL((tau_skew_persistent_kernel<NWAVES, REC>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((tau_skew_persistent_kernel<NWAVES, REC, M>), dim3((unsigned)grid),
                        dim3(NT), 0, st, b, items, (int)n, queue, tau);
   };
   return v;
@@ -855,7 +869,8 @@ const VariantFns &variant_fns(int v) {
       make_skew_variant<2>(),
       make_variant<8, 4, 512>(),
       make_variant<8, 2, 512>(),
-      make_skew_variant<4, true>(),  // the Gaussian recurrence across a lane's targets
+      make_skew_variant<4, true>(),     // the Gaussian recurrence across a lane's targets
+      make_skew_variant<4, true, 8>(),  // the same over 8 targets per lane
   };
   return table[v];
 }
@@ -863,7 +878,7 @@ const VariantFns &variant_fns(int v) {
 
 const TauVariant kTauVariants[kNumTauVariants] = {
     {1, kSkewM, SkewShape<4>::kTile}, {1, kSkewM, SkewShape<2>::kTile}, {8, 4, 512}, {8, 2, 512},
-    {1, kSkewM, SkewShape<4>::kTile}};
+    {1, kSkewM, SkewShape<4>::kTile}, {1, 8, SkewShape<4, 8>::kTile}};
 
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items, float *tau,
                              hipStream_t st, int variant, int persistent_grid,

@@ -31,7 +31,7 @@ LYAF_OK, LYAF_EINVAL, LYAF_EDOMAIN, LYAF_ENOROOT = 0, -1, -2, -3
 LYAF_ENOCONV, LYAF_EDEVICE, LYAF_ENOMEM = -4, -5, -6
 STATUS_DOMAIN, STATUS_NOROOT, STATUS_NOCONV = 1, 2, 4
 FLAG_PLAIN, FLAG_PER_SKEWER, FLAG_PERSISTENT = 1, 2, 4
-NUM_SHAPES = 5
+NUM_SHAPES = 6
 PLAN_AUTOTUNE, PLAN_NO_GRAPH = 1, 2
 
 

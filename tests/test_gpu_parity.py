@@ -101,16 +101,18 @@ def test_tau_cold_unresolved_sources_and_inverted_relation():
         assert_tau_close(got, ref, f"cold pivot={pivot}")
 
 
-@pytest.mark.parametrize("shape", [0, 4])
+@pytest.mark.parametrize("shape", [0, 4, 5])
 def test_tau_recurrence_shape_near_and_past_its_limit(shape):
-    """The recurrence shape (4) on isothermal skewers whose lines are narrow
-    against the pixels: a = dv sqrt(log2 e) / b of 0.37, 0.93 (the recurrence
-    close to its limit of 1) and 1.08 (the tile falls back to the direct
-    form), against the oracle; shape 0 on the same skewers for comparison."""
+    """The recurrence shapes (4: 4 targets per lane, limit a <= 1; 5: 8 targets,
+    limit a <= 0.45) on isothermal skewers whose lines are narrow against the
+    pixels: a = dv sqrt(log2 e) / b of 0.37, 0.43 (shape 5 close to its limit),
+    0.93 (shape 4 close to its limit, shape 5 past it) and 1.08 (both fall back
+    to the direct form), against the oracle; shape 0 on the same skewers for
+    comparison."""
     from paper_1105_4747_amd import lyaf as L
-    w = fields.small_workload(n_skewers=3, n_pix=3000, seed=41, dv=4.0, sigma_lnD=1.5)
+    w = fields.small_workload(n_skewers=4, n_pix=5000, seed=41, dv=4.0, sigma_lnD=1.5)
     w.gamma[:] = 1.0
-    w.T0[:] = np.array([1e4, 1.6e3, 1.2e3], np.float32)
+    w.T0[:] = np.array([1e4, 7.6e3, 1.6e3, 1.2e3], np.float32)
     print(f"case: narrow lines shape={shape}", flush=True)
     got = gpu_tau(w, flags=L.FLAG_SHAPE(shape)).cpu().numpy()
     assert_tau_close(got, oracle_tau(w), f"narrow lines shape {shape}")
