@@ -242,6 +242,8 @@ int ensure_plan(Workspace *ws, const lyaf_skewers *sk, int tile, HostPlan **out)
 struct HostInsPlan {
   std::vector<int64_t> offsets, out_offsets;  // [S+1] each
   int64_t n_items = 0;
+  int64_t n_sk = 0;   // backward: skewers for the per-skewer kernel (after the items)
+  int max_bins = 0;   // the most bins of those skewers
   int64_t *h_off = nullptr, *h_oo = nullptr;
   int2 *h_items = nullptr;
   int64_t h_off_cap = 0, h_oo_cap = 0, h_items_cap = 0;
@@ -292,17 +294,22 @@ int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int6
   // the pinned staging buffers may still feed an earlier copy on this stream
   if ((e = hipStreamSynchronize(ws->stream)) != hipSuccess) return map_err(e);
   hp.offsets.clear();
-  int64_t ni = 0;
-  for (int64_t s = 0; s < S; ++s)
-    ni += ins_items_per_skewer(offsets[s + 1] - offsets[s], out_offsets[s + 1] - out_offsets[s],
-                               backward);
-  if (ni > INT32_MAX) return LYAF_EINVAL;
+  int64_t ni = 0, nf = 0, max_bins = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t n = offsets[s + 1] - offsets[s], no = out_offsets[s + 1] - out_offsets[s];
+    ni += ins_items_per_skewer(n, no, backward);
+    if (backward && ins_bwd_skewer_item(n, no)) {
+      ++nf;
+      max_bins = std::max(max_bins, no);
+    }
+  }
+  if (ni + nf > INT32_MAX) return LYAF_EINVAL;
   if ((e = grow_host(hp.h_off, hp.h_off_cap, S + 1)) != hipSuccess ||
       (e = grow_host(hp.h_oo, hp.h_oo_cap, S + 1)) != hipSuccess ||
-      (e = grow_host(hp.h_items, hp.h_items_cap, ni)) != hipSuccess ||
+      (e = grow_host(hp.h_items, hp.h_items_cap, ni + nf)) != hipSuccess ||
       (e = grow_dev(hp.d_off, hp.d_off_cap, S + 1)) != hipSuccess ||
       (e = grow_dev(hp.d_oo, hp.d_oo_cap, S + 1)) != hipSuccess ||
-      (e = grow_dev(hp.d_items, hp.d_items_cap, ni)) != hipSuccess)
+      (e = grow_dev(hp.d_items, hp.d_items_cap, ni + nf)) != hipSuccess)
     return map_err(e);
   memcpy(hp.h_off, offsets, sizeof(int64_t) * (size_t)(S + 1));
   memcpy(hp.h_oo, out_offsets, sizeof(int64_t) * (size_t)(S + 1));
@@ -312,16 +319,23 @@ int ensure_ins_plan(Workspace *ws, int64_t S, const int64_t *offsets, const int6
                                        out_offsets[s + 1] - out_offsets[s], backward);
     for (int t = 0; t < c; ++t) hp.h_items[k++] = make_int2((int)s, t);
   }
+  if (backward)
+    for (int64_t s = 0; s < S; ++s)
+      if (ins_bwd_skewer_item(offsets[s + 1] - offsets[s], out_offsets[s + 1] - out_offsets[s]))
+        hp.h_items[k++] = make_int2((int)s, 0);
   if ((e = hipMemcpyAsync(hp.d_off, hp.h_off, sizeof(int64_t) * (size_t)(S + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(hp.d_oo, hp.h_oo, sizeof(int64_t) * (size_t)(S + 1),
                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess ||
-      (ni > 0 && (e = hipMemcpyAsync(hp.d_items, hp.h_items, sizeof(int2) * (size_t)ni,
-                                     hipMemcpyHostToDevice, ws->stream)) != hipSuccess))
+      (ni + nf > 0 &&
+       (e = hipMemcpyAsync(hp.d_items, hp.h_items, sizeof(int2) * (size_t)(ni + nf),
+                           hipMemcpyHostToDevice, ws->stream)) != hipSuccess))
     return map_err(e);
   hp.offsets.assign(offsets, offsets + S + 1);
   hp.out_offsets.assign(out_offsets, out_offsets + S + 1);
   hp.n_items = ni;
+  hp.n_sk = nf;
+  hp.max_bins = (int)max_bins;
   return LYAF_OK;
 }
 
@@ -662,8 +676,9 @@ int lyaf_instrument(int64_t n_skewers, const int64_t *offsets, const float *dv, 
   a.in = F;
   a.out = F_obs;
   a.noise = ip->noise_sigma > 0.0 ? noise : nullptr;
-  return map_err(timed("instrument", st,
-                       [&] { return launch_instrument(a, hp->d_items, hp->n_items, false, st); }));
+  return map_err(timed("instrument", st, [&] {
+    return launch_instrument(a, hp->d_items, hp->n_items, nullptr, 0, 0, false, st);
+  }));
 }
 
 int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const float *dv,
@@ -683,8 +698,10 @@ int lyaf_instrument_backward(int64_t n_skewers, const int64_t *offsets, const fl
   InsArgs a = make_ins_args(ws, hp, dv, ip);
   a.in = grad_obs;
   a.out = grad_F;
-  return map_err(timed("instrument_backward", st,
-                       [&] { return launch_instrument(a, hp->d_items, hp->n_items, true, st); }));
+  return map_err(timed("instrument_backward", st, [&] {
+    return launch_instrument(a, hp->d_items, hp->n_items, hp->d_items + hp->n_items, hp->n_sk,
+                             hp->max_bins, true, st);
+  }));
 }
 
 int lyaf_flux_pdf(int64_t n_pix, const float *F, int64_t *counts, void *stream) {

@@ -31,9 +31,14 @@
 // difference of that cumulative integral, linearly interpolated, at its two
 // edges, divided by its width.
 //
-// The backward kernel is the transpose: each pixel gathers the gradients of
-// the bins it overlaps (times overlap / bin width), and the same convolution
-// runs over those values (the taps are even in m).
+// The backward is the transpose: each pixel gathers the gradients of the bins
+// it overlaps (times overlap / bin width), and the same convolution runs over
+// those values (the taps are even in m).  Skewers with at most kInsBwdBins
+// bins take one workgroup each, which forms the bins' FP64 prefix sums once in
+// LDS (a pixel's gathered gradient is then the difference of their linear
+// interpolation at its two edges) and walks the skewer's tiles; skewers with
+// more bins take one workgroup per tile and gather by a merge walk over the
+// bins in memory.
 #include <algorithm>
 
 #include "lyaf_internal.h"
@@ -140,24 +145,27 @@ __device__ double block_sum_d(double v, double *red) {
   return t;
 }
 
+// The unnormalised tap at offset m, |m| <= M: g(m dv), halved at the two ends
+// of a whole even box; scale = dv / b_L.
+__device__ inline double tap_value(const InsArgs &a, const InsSkewer &k, int m, double scale) {
+  if (!(a.fwhm > 0.0)) return 1.0;  // M = 0: the identity
+  const double x = (double)m * scale;
+  double g = exp(-x * x);
+  if (k.half_ends && (m == k.M || m == -k.M)) g *= 0.5;
+  return g;
+}
+__device__ inline double tap_scale(const InsArgs &a, const InsSkewer &k) {
+  return a.fwhm > 0.0 ? k.dv / (a.fwhm * kInvTwoSqrtLn2) : 0.0;
+}
+
 // Taps u0 .. u0 + tbp - 1 of the walk (h_u = g((M - u) dv), zero past the tb
 // real ones) into sh.h; returns this thread's share of their sum.
 __device__ double stage_taps(const InsArgs &a, const InsSkewer &k, int u0, int tb, int tbp,
                              double *h) {
   double z_part = 0.0;
-  const double scale = a.fwhm > 0.0 ? k.dv / (a.fwhm * kInvTwoSqrtLn2) : 0.0;  // dv / b_L
+  const double scale = tap_scale(a, k);
   for (int u = threadIdx.x; u < tbp; u += kInsThreads) {
-    double g = 0.0;
-    if (u < tb) {
-      const int m = k.M - (u0 + u);
-      if (a.fwhm > 0.0) {
-        const double x = (double)m * scale;
-        g = exp(-x * x);
-        if (k.half_ends && (m == k.M || m == -k.M)) g *= 0.5;
-      } else {
-        g = 1.0;  // M = 0: the identity
-      }
-    }
+    const double g = u < tb ? tap_value(a, k, k.M - (u0 + u), scale) : 0.0;
     h[u] = g;
     z_part += g;
   }
@@ -558,27 +566,17 @@ __device__ inline void bin_adjoint_run(const InsArgs &a, const InsSkewer &k, con
     if (p < cnt) out(p, acc[p]);
 }
 
-// LDS of the backward when the taps fit one block: the binning adjoint of the
-// tile's staged pixels (FP32, planes as in the forward), the taps, and the
-// skewer's bin gradients when there are at most kInsBwdBins of them.
+// LDS of the per-tile backward when the taps fit one block: the binning
+// adjoint of the tile's staged pixels (FP32, planes as in the forward) and the
+// taps.  That kernel takes the skewers with more than kInsBwdBins bins (read
+// from memory) or none; the per-skewer kernel below takes the others.
 constexpr int kInsBwdBins = 4096;
 struct InsBwdShared {
   float f[8 * kDmaRows];
   double h[kInsTapBlock];
   double red[kInsThreads / 64];
-  float gb[kInsBwdBins];
 };
 
-// Copy of g[0 .. n_out) into LDS, 64 values per wave instruction
-// (global_load_lds; lanes past the end reload the last value).
-__device__ inline void bins_dma(const float *g, int64_t n_out, float *gb) {
-  const int lane = threadIdx.x & 63;
-  const int nch = (int)((n_out + 63) >> 6);
-  for (int c = threadIdx.x >> 6; c < nch; c += kInsThreads / 64) {
-    const int64_t j = min<int64_t>(64 * (int64_t)c + lane, n_out - 1);
-    __builtin_amdgcn_global_load_lds(g + j, gb + 64 * c, 4, 0, 0);
-  }
-}
 union InsBwdLds {
   InsShared w;     // wide line-spread functions
   InsBwdShared d;  // taps in one block
@@ -620,36 +618,26 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
   if (T <= kInsTapBlock) {
     InsBwdShared &d = lds.d;
     const int tbp = (T + 15) & ~15;
-    const bool lds_g = k.n_out <= kInsBwdBins;
-    if (lds_g) bins_dma(g, k.n_out, d.gb);  // in flight while the taps are formed
     const double z_part = stage_taps(a, k, 0, T, tbp, d.h);
-    if (lds_g) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();  // every wave's copy is complete
     const int rows = (span + tbp - 1 + 7) >> 3;  // staged offsets read by outputs < span
-    const auto stage_row = [&](auto gload) {
-      for (int r = threadIdx.x; r < rows; r += kInsThreads) {
-        // staged offsets 8r .. 8r + 7 are pixels (base + x) mod n, consecutive
-        // up to the end of the box
-        uint32_t i = base + 8u * (uint32_t)r;
-        if (i >= n32) i -= n32;
-        if (i >= n32) i %= n32;
-        int done = 0;
-        while (done < 8) {
-          const int c = min(8 - done, (int)(n32 - i));
-          const int x0 = 8 * r + done;
-          bin_adjoint_run(a, k, G, (int64_t)i, c, gload, [&](int p, double v) {
-            const int x = x0 + p;
-            d.f[(x & 7) * kDmaRows + (x >> 3)] = (float)v;
-          });
-          done += c;
-          i = 0;
-        }
+    for (int r = threadIdx.x; r < rows; r += kInsThreads) {
+      // staged offsets 8r .. 8r + 7 are pixels (base + x) mod n, consecutive
+      // up to the end of the box
+      uint32_t i = base + 8u * (uint32_t)r;
+      if (i >= n32) i -= n32;
+      if (i >= n32) i %= n32;
+      int done = 0;
+      while (done < 8) {
+        const int c = min(8 - done, (int)(n32 - i));
+        const int x0 = 8 * r + done;
+        bin_adjoint_run(a, k, G, (int64_t)i, c, g_global, [&](int p, double v) {
+          const int x = x0 + p;
+          d.f[(x & 7) * kDmaRows + (x >> 3)] = (float)v;
+        });
+        done += c;
+        i = 0;
       }
-    };
-    if (lds_g)
-      stage_row([&](int64_t kb) -> float { return d.gb[kb]; });
-    else
-      stage_row(g_global);
+    }
     Z = block_sum_d(z_part, d.red);  // its barriers publish the staged values and the taps
 #pragma unroll
     for (int q = 0; q < kInsPerLane; ++q) acc[q] = 0.0;
@@ -672,21 +660,190 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_kernel(
     if (t0 + q < span) gF[p0 + t0 + q] = (float)(acc[q] * invZ);
 }
 
+// Backward, one workgroup per skewer whose bins fit LDS (the per-tile kernel
+// takes the skewers with more bins or none).  The binning adjoint of pixel
+// [y, y + 1) (pixel coordinates, one image of the pixel) is C(y + 1) - C(y),
+// where C is the integral of the bins' gradient density g_k / (bin width) from
+// the first bin's lower edge, in pixel units: C = P[k] + t (P[k+1] - P[k]) at
+// bin coordinate k + t (t in [0, 1); a pixel is 1 / q bin units, so the
+// difference carries the 1 / q), with the prefix sums P[k] = sum_{k' < k} g_k'
+// (C is 0 before the first bin and P[n_out] past the last), summed over the
+// pixel's images that meet the bins.  P (FP64, n_out + 1 values, dynamic LDS)
+// and the taps' sum are formed once; the skewer's tiles of kInsTile pixels are
+// walked, each thread forming the adjoint of rows of eight staged pixels (tile
+// + taps, FP32 in planes as in the per-tile kernel) and the tile convolved
+// block of taps by block.  A wave whose staged window is all zero (pixels that
+// no bin reaches within the taps) stores zeros without convolving.
+struct InsBwdSkShared {
+  float f[8 * kDmaRows];
+  double h[kInsTapBlock];
+  double red[kInsThreads / 64];
+  double tot[kInsThreads / 64];
+  uint8_t nz_row[kDmaRows];  // row r of the staged block holds a nonzero value
+};
+constexpr int kBwdPerThread = kInsBwdBins / kInsThreads;  // bins per thread in the prefix sums
+static_assert(kBwdPerThread * kInsThreads == kInsBwdBins, "the prefix sums cover every bin");
+static_assert(64 + kInsTapBlock / 8 <= 128, "a wave's staged rows are two per lane at most");
+
+__global__ __launch_bounds__(kInsThreads) void instrument_backward_skewer_kernel(
+    InsArgs a, const int2 *__restrict__ items) {
+  __shared__ InsBwdSkShared sh;
+  extern __shared__ double P[];  // n_out + 1 prefix sums
+  const InsSkewer k = ins_skewer(a, items[blockIdx.x].x);
+  if (!k.ok) {
+    if (threadIdx.x == 0) atomicOr(a.status, LYAF_STATUS_DOMAIN);
+    return;
+  }
+  const int nb = (int)k.n_out;
+  const float *g = a.in + k.out_off;
+  // P[j + 1] = sum_{j' <= j} g_j': thread t sums bins 16t .. 16t + 15, then the
+  // workgroup scans the threads' totals
+  double v[kBwdPerThread];
+  const int j0 = (int)threadIdx.x * kBwdPerThread;
+#pragma unroll
+  for (int j = 0; j < kBwdPerThread; ++j) v[j] = j0 + j < nb ? (double)g[j0 + j] : 0.0;
+  const int T = 2 * k.M + 1;
+  const bool one_block = T <= kInsTapBlock;
+  // the taps' sum (and, when they fit one block, the taps themselves)
+  double z_part = 0.0;
+  if (one_block) {
+    z_part = stage_taps(a, k, 0, T, (T + 15) & ~15, sh.h);
+  } else {
+    const double scale = tap_scale(a, k);
+    for (int u = threadIdx.x; u < T; u += kInsThreads) z_part += tap_value(a, k, k.M - u, scale);
+  }
+#pragma unroll
+  for (int j = 1; j < kBwdPerThread; ++j) v[j] += v[j - 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double incl = v[kBwdPerThread - 1];
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = __shfl_up(incl, d);
+    if (lane >= d) incl += o;
+  }
+  if (lane == 63) sh.tot[wv] = incl;
+  double excl = __shfl_up(incl, 1);
+  if (lane == 0) excl = 0.0;
+  __syncthreads();
+  for (int w = 0; w < wv; ++w) excl += sh.tot[w];
+  if (threadIdx.x == 0) P[0] = 0.0;
+#pragma unroll
+  for (int j = 0; j < kBwdPerThread; ++j)
+    if (j0 + j < nb) P[j0 + j + 1] = excl + v[j];
+  const double invZ = 1.0 / block_sum_d(z_part, sh.red);  // its barriers publish P and the taps
+
+  const double x_first = bin_edge(a, k, 0), x_last = bin_edge(a, k, k.n_out);
+  const double nd = (double)(int)k.n, inv_nd = 1.0 / nd;
+  const double Ptot = P[nb];
+  const auto cum = [&](double y) -> double {
+    const double t = (y - x_first) * k.inv_q;
+    if (!(t > 0.0)) return 0.0;
+    if (t >= (double)nb) return Ptot;
+    const int kb = (int)t;
+    return __builtin_fma(t - (double)kb, P[kb + 1] - P[kb], P[kb]);
+  };
+  const uint32_t n32 = (uint32_t)k.n;
+  float *gF = a.out + k.off;
+  const int n_tiles = (int)((k.n + kInsTile - 1) / kInsTile);
+  bool first = true;  // no barrier owed to earlier readers of f and h
+  for (int c = 0; c < n_tiles; ++c) {
+    const int64_t p0 = (int64_t)c * kInsTile;
+    const int span = (int)min<int64_t>(kInsTile, k.n - p0);
+    const bool wave_active = (int)(threadIdx.x & ~63u) * kInsPerLane < span;
+    double acc[kInsPerLane];
+#pragma unroll
+    for (int q = 0; q < kInsPerLane; ++q) acc[q] = 0.0;
+    for (int u0 = 0; u0 < T; u0 += kInsTapBlock) {
+      const int tb = min(kInsTapBlock, T - u0);  // real taps in this block
+      const int tbp = (tb + 15) & ~15;           // walked taps (zero-padded)
+      if (!first) __syncthreads();  // every wave is done with the previous block's values
+      first = false;
+      if (!one_block) stage_taps(a, k, u0, tb, tbp, sh.h);
+      // staged offset x is pixel (p0 - M + u0 + x) mod n
+      const uint32_t base = (uint32_t)wrap_index(p0 - k.M + u0, (int)k.n);
+      const int rows = (span + tbp - 1 + 7) >> 3;  // staged offsets read by outputs < span
+      for (int r = threadIdx.x; r < rows; r += kInsThreads) {
+        // staged offsets 8r .. 8r + 7: pixels consecutive up to the end of the box
+        uint32_t i = base + 8u * (uint32_t)r;
+        if (i >= n32) i -= n32;
+        if (i >= n32) i %= n32;
+        int done = 0;
+        bool any = false;
+        while (done < 8) {
+          const int cnt = min(8 - done, (int)(n32 - i));
+          double G[8];
+#pragma unroll
+          for (int p = 0; p < 8; ++p) G[p] = 0.0;
+          // images y = i + L n of the run's pixels that meet [x_first, x_last)
+          const double L_lo = ceil((x_first - (double)(i + cnt - 1) - 1.0) * inv_nd);
+          const double L_hi = floor((x_last - (double)i) * inv_nd);
+          for (double L = L_lo; L <= L_hi; L += 1.0) {
+            const double y0 = __builtin_fma(L, nd, (double)i);
+            double c0 = cum(y0);
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+              if (p < cnt) {
+                const double c1 = cum(y0 + (double)(p + 1));
+                G[p] += c1 - c0;
+                c0 = c1;
+              }
+            }
+          }
+          const int x0 = 8 * r + done;
+#pragma unroll
+          for (int p = 0; p < 8; ++p) {
+            if (p < cnt) {
+              const int x = x0 + p;
+              const float gv = (float)G[p];
+              any |= gv != 0.0f;
+              sh.f[(x & 7) * kDmaRows + (x >> 3)] = gv;
+            }
+          }
+          done += cnt;
+          i = 0;
+        }
+        sh.nz_row[r] = any ? 1 : 0;
+      }
+      __syncthreads();
+      // rows 64 w .. 64 w + 63 + tbp / 8 feed wave w's outputs
+      const int r0 = (int)(threadIdx.x & ~63u) + lane;
+      const int r1 = r0 + 64;
+      const bool mine = (r0 < rows && sh.nz_row[r0]) ||
+                        (lane <= tbp / 8 - 1 && r1 < rows && sh.nz_row[r1]);
+      if (wave_active && __any(mine)) conv_block_f32(tbp, acc, sh.f, sh.h);
+    }
+    const int t0 = threadIdx.x * kInsPerLane;
+#pragma unroll
+    for (int q = 0; q < kInsPerLane; ++q)
+      if (t0 + q < span) gF[p0 + t0 + q] = (float)(acc[q] * invZ);
+  }
+}
+
 }  // namespace
+
+bool ins_bwd_skewer_item(int64_t n, int64_t n_out) {
+  return n > 0 && n_out > 0 && n_out <= kInsBwdBins;
+}
 
 int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward) {
   if (n <= 0) return 0;
-  if (backward) return (int)((n + kInsTile - 1) / kInsTile);
+  if (backward)  // skewers with 1 .. kInsBwdBins bins go to the per-skewer kernel
+    return ins_bwd_skewer_item(n, n_out) ? 0 : (int)((n + kInsTile - 1) / kInsTile);
   return n_out > 0 ? 1 : 0;  // the forward takes a whole skewer per workgroup
 }
 
-hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items, bool backward,
-                             hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
+hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items,
+                             const int2 *skewer_items, int64_t n_skewer_items, int max_bins,
+                             bool backward, hipStream_t st) {
   if (backward) {
-    hipLaunchKernelGGL(instrument_backward_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0,
-                       st, a, items);
-  } else {
+    // each skewer is taken by exactly one of the two kernels
+    if (n_skewer_items > 0)
+      hipLaunchKernelGGL(instrument_backward_skewer_kernel, dim3((unsigned)n_skewer_items),
+                         dim3(kInsThreads), sizeof(double) * (size_t)(max_bins + 1), st, a,
+                         skewer_items);
+    if (n_items > 0)
+      hipLaunchKernelGGL(instrument_backward_kernel, dim3((unsigned)n_items), dim3(kInsThreads),
+                         0, st, a, items);
+  } else if (n_items > 0) {
     hipLaunchKernelGGL(instrument_kernel, dim3((unsigned)n_items), dim3(kInsThreads), 0, st, a,
                        items);
   }

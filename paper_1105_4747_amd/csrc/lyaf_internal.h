@@ -160,8 +160,14 @@ struct InsArgs {
   uint32_t *status;
 };
 int ins_items_per_skewer(int64_t n, int64_t n_out, bool backward);
-hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items, bool backward,
-                             hipStream_t st);
+// Whether the backward's per-skewer kernel takes a skewer (its bins fit that
+// kernel's LDS); the per-tile kernel's items cover the others.
+bool ins_bwd_skewer_item(int64_t n, int64_t n_out);
+// skewer_items: the backward's per-skewer items, max_bins the most bins of
+// their skewers (ignored by the forward).
+hipError_t launch_instrument(const InsArgs &a, const int2 *items, int64_t n_items,
+                             const int2 *skewer_items, int64_t n_skewer_items, int max_bins,
+                             bool backward, hipStream_t st);
 // Flux statistics (flux PDF, 1D flux power spectrum).
 constexpr int kPdfMaxBlocks = 1024;  // workgroups of the PDF counting kernel
 constexpr int kPdfCountSlots = 24;   // 21 bins, below, above, NaN

@@ -793,7 +793,7 @@ __global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
 // grid form
 template <int NWAVES, bool REC, int M>
 __global__ __launch_bounds__(NWAVES * kWave)
-__attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
+__attribute__((amdgpu_waves_per_eu(NWAVES == 4 && M == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
     Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
     float *__restrict__ tau) {
   __shared__ float4 rec[SkewShape<NWAVES, M>::kChunkS + 4];

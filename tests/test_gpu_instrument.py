@@ -69,6 +69,12 @@ CASES = {
     # boxes shorter than one thread's row of eight staged pixels (the row wraps
     # around the box more than once)
     "tiny-boxes": ([3, 5, 7, 1], [2.0, 2.0, 2.0, 2.0], 3.0, 1.5, -0.7, 6.0, None),
+    # 4096 bins (the most the per-skewer adjoint holds in LDS) and 4097 (the
+    # per-tile adjoint), with a bin edge on every other pixel edge
+    "bins-at-the-lds-limit": ([8192, 8194], [1.0, 1.0], 7.0, 2.0, -3.0, 6.0, None),
+    # short taps on short boxes (3 taps on 9 and 13 pixels; the 2-pixel box
+    # takes the whole-box form), bins starting several boxes away
+    "short-taps-short-boxes": ([9, 13, 2], [2.0, 2.0, 2.0], 1.0, 1.5, -47.3, 6.0, None),
 }
 
 
