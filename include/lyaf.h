@@ -117,9 +117,10 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out,
              void *stream);
 
 /* Mean-flux renormalisation (Section 2.3, last paragraph): solve
- * (1/P) sum_p exp(-A tau_p) = target_F for A in FP64 on the device (safeguarded
- * Newton/Halley from the Jensen lower bound, FP64 sums), then write
- * tau' = A tau and F = exp(-tau').
+ * (1/P) sum_p exp(-A tau_p) = target_F for A in FP64 on the device (from the
+ * root on a sample of the pixels, a step to the root of the series of the
+ * mean flux about it, with safeguarded Newton/Halley steps as the fallback;
+ * FP64 sums), then write tau' = A tau and F = exp(-tau').
  *   tau_inout: DEVICE [n_pix] float; raw tau in, A*tau out (may not alias F_out).
  *   F_out:     DEVICE [n_pix] float, written (may be NULL to skip).
  *   A_dev:     DEVICE double, written with A.

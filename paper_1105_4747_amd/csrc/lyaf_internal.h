@@ -92,12 +92,14 @@ struct Workspace {
 constexpr int kMaxPartialBlocks = 512;  // workgroups of a root-find pass
 constexpr int kPartStride = 8;          // doubles per workgroup partial
 constexpr int kNormPasses = 3;          // full root-find passes after the sample
-constexpr int kSampleN = 16384;         // pixels the root-find samples first
-// The partials allocation also holds the sample (kSampleN floats) after the
-// two partial buffers.
-constexpr int64_t kPartialsDoubles = 2 * kPartStride * kMaxPartialBlocks + kSampleN / 2;
+constexpr int kSampleN = 8192;          // pixels the root-find samples first
+constexpr int kSampleCap = 16384;       // room for the sample in the partials allocation
+// The partials allocation also holds the sample (up to kSampleCap floats)
+// after the two partial buffers.
+constexpr int64_t kPartialsDoubles = 2 * kPartStride * kMaxPartialBlocks + kSampleCap / 2;
+static_assert(kSampleN <= kSampleCap, "the sample fits its room");
 constexpr double kNormAcceptStep = 1e-5;
-// Largest batch of the mean-flux root-find: the sample index k P / 16384 is
+// Largest batch of the mean-flux root-find: the sample index k P / kSampleN is
 // formed in int64 (2^48 pixels is a petabyte of tau, far beyond any device).
 constexpr int64_t kMaxNormPixels = int64_t(1) << 48;
 

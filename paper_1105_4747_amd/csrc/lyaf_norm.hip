@@ -5,32 +5,38 @@
 // The root-find runs on the device without host synchronisation, as a short
 // fixed sequence of kernels (each kernel boundary costs a few microseconds,
 // so there are few):
-//   norm_gather    16384 pixels spread evenly over the batch (all of them if
+//   norm_gather    8192 pixels spread evenly over the batch (all of them if
 //                  fewer) into a contiguous buffer;
 //   norm_sample    one workgroup keeps the sample in registers and iterates
 //                  to convergence on it, starting from the Jensen
 //                  lower bound A0 = -ln F / <tau> (g(A0) >= 0 for the convex,
 //                  decreasing g(A) = <exp(-A tau)> - F); FP32 exponentials,
-//                  FP64 sums.  The sample's root is within ~1.5e-2 of the
-//                  batch's (the sampling error of g is ~3e-3).
-//   norm_pass x3   S_k = sum tau^k exp(-A tau), k = 0, 1, 2, over every
-//                  pixel, in FP64 per workgroup, with the counts of zero and
-//                  invalid values; FP32 exponentials until a step is below
-//                  3e-2 of A, then FP64 exponentials (to 1e-13) until a step
-//                  is below 1e-5.  Each pass begins with every workgroup summing the
-//                  previous pass's partials in the same fixed order and taking
-//                  the same safeguarded Halley step (Newton, then bisection,
-//                  as fallbacks) inside the bracket.  A kernel boundary, not a
-//                  device-scope fence, publishes the partials: on a multi-XCD
-//                  part a fence per workgroup writes back and invalidates L2
-//                  and serialises the pass.
+//                  FP64 sums.  The sample's root is within a few 1e-2 of the
+//                  batch's (the sampling error of g is a few 1e-3).
+//   norm_pass x3   S_k = sum tau^k exp(-A tau) over every pixel, in FP64 per
+//                  workgroup, with the counts of zero and invalid values.
+//                  After a settled sample the passes are exact from the
+//                  first: FP64 exponentials (to 1e-13), k = 0 .. 5.  Each
+//                  pass begins with every workgroup summing the previous
+//                  pass's partials in the same fixed order and taking the
+//                  same step: the root of the degree-5 Taylor series of g
+//                  about A (the scaled moments M_k = A^k S_k / P are its
+//                  coefficients up to sign and k!), accepted at once when it
+//                  is below 0.1 of A and the degree-4 series' root agrees
+//                  with it to 1e-8; otherwise a safeguarded Halley step
+//                  (Newton, then bisection, as fallbacks) inside the bracket,
+//                  accepted below 1e-5 of A.  A sample without a settled root
+//                  starts the passes with FP32 exponentials and k = 0 .. 2
+//                  until a Halley step is below 3e-2 of A.  A kernel
+//                  boundary, not a device-scope fence, publishes the
+//                  partials: on a multi-XCD part a fence per workgroup
+//                  writes back and invalidates L2 and serialises the pass.
 //   norm_finalise  the last step, then tau' = A tau and F = exp(-tau').
-// Halley converges cubically: a step of 3e-2 leaves an iterate ~K 3e-5 off
-// (K, the ratio of successive errors to the cube, is below 0.1 on
-// lognormal-field tau), so one FP32 pass and one FP64 pass usually suffice
-// and the FP64 step that follows is accepted; the third pass is a reserve,
-// and a pass with nothing left to do returns at once.  Results are bitwise
-// reproducible.
+// From a sample root a few 1e-2 off, the degree-5 series' root is within
+// ~1e-11 of the batch's root and the degree-4 one within ~1e-9 (lognormal-
+// field tau), so one exact pass usually suffices: the second pass takes the
+// step and returns, and the third (a reserve for the Halley iteration) and the
+// finalisation find nothing left to do.  Results are bitwise reproducible.
 #include <math.h>
 
 #include <mutex>
@@ -93,9 +99,13 @@ __device__ __forceinline__ double exp_neg_tab(double x, const double *tab) {
   return (x <= 708.0) ? e : 0.0;
 }
 
-// Sum of N values over a workgroup of NW waves (fixed order).
+// Sum of N values over a workgroup of NW waves (fixed order), in every
+// thread.  For many values thread q < N adds up quantity q's NW wave sums, so
+// that no thread holds all N NW of them in registers at once (an extra
+// barrier); few are added up by every thread.  sh holds N (NW + 1) doubles.
+constexpr int block_sum_lds(int N, int NW) { return N * (NW + 1); }
 template <int N, int NW>
-__device__ __forceinline__ void block_sum(double (&v)[N], double *sh /*[N*NW]*/) {
+__device__ __forceinline__ void block_sum(double (&v)[N], double *sh) {
 #pragma unroll
   for (int q = 0; q < N; ++q)
     for (int m = 32; m >= 1; m >>= 1) v[q] += __shfl_xor(v[q], m);
@@ -104,12 +114,25 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *sh /*[N*NW]*/)
 #pragma unroll
     for (int q = 0; q < N; ++q) sh[q * NW + w] = v[q];
   __syncthreads();
+  if constexpr (N * NW <= 16) {
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
-    double t = sh[q * NW];
+    for (int q = 0; q < N; ++q) {
+      double t = sh[q * NW];
 #pragma unroll
-    for (int k = 1; k < NW; ++k) t += sh[q * NW + k];
-    v[q] = t;
+      for (int k = 1; k < NW; ++k) t += sh[q * NW + k];
+      v[q] = t;
+    }
+  } else {
+    if (threadIdx.x < N) {
+      const double *r = sh + threadIdx.x * NW;
+      double t = r[0];
+#pragma unroll
+      for (int k = 1; k < NW; ++k) t += r[k];
+      sh[N * NW + threadIdx.x] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = sh[N * NW + q];
   }
   __syncthreads();
 }
@@ -130,15 +153,24 @@ constexpr int kNormThreads = 256;  // backward kernels and finalise
 constexpr int kNormWaves = kNormThreads / kWave;
 constexpr int kPassThreads = 512;  // full root-find passes
 constexpr int kPassWaves = kPassThreads / kWave;
-constexpr int kNormQ = 5;          // S0, S1, S2, #(tau = 0), #(invalid tau)
+// per-workgroup partials of a pass: S_0 .. S_5, #(tau = 0), #(invalid tau)
+constexpr int kNormQ = 8;
+constexpr int kQZero = 6, kQBad = 7;
+static_assert(kNormQ <= kPartStride, "a workgroup's partials fit its slot");
 constexpr int kSampleThreads = 256;
 constexpr int kSampleWaves = kSampleThreads / kWave;
 constexpr int kGatherThreads = 256;
 constexpr int kSampleIters = 32;
 // the sample iteration stops at this step: its root is only ~1e-2 from the
-// batch's, and FP32 moments would not let it settle much below 1e-7
-constexpr double kSampleTol = 1e-4;
+// batch's, which the first full pass's series step corrects
+constexpr double kSampleTol = 1e-3;
 constexpr double kFP32Accept = 3e-2;
+// An exact-phase step from the degree-5 Taylor model of g is accepted at once
+// when it is at most kTaylorMaxStep of A and the degree-4 model's root agrees
+// with it to kTaylorAgree (the next term of the series, which bounds the
+// degree-5 root's error, is then smaller by another factor of the step).
+constexpr double kTaylorMaxStep = 0.1;
+constexpr double kTaylorAgree = 1e-8;
 
 // One safeguarded Halley step for g, g' = g1, g'' = g2 at s.A, narrowing the
 // bracket; sets s.A and s.step = |A_new - A_old| / A_new.
@@ -160,7 +192,7 @@ __device__ __forceinline__ void halley(NormState &s, double g, double g1, double
 }
 
 // The sample: pixel floor(k P / N) for k < N = min(P, kSampleN), gathered by
-// many workgroups into a contiguous buffer (one workgroup pulling 16384
+// many workgroups into a contiguous buffer (one workgroup pulling thousands of
 // scattered cache lines alone would take tens of microseconds).
 __global__ __launch_bounds__(kGatherThreads) void norm_gather_kernel(
     const float *__restrict__ tau, int64_t P, float *__restrict__ sample) {
@@ -174,7 +206,7 @@ __global__ __launch_bounds__(kGatherThreads) void norm_gather_kernel(
 // yet).
 __global__ __launch_bounds__(kSampleThreads) void norm_sample_kernel(
     const float *__restrict__ sample, int64_t P, double target, NormState *st_out) {
-  __shared__ double sh[3 * kSampleWaves];
+  __shared__ double sh[block_sum_lds(3, kSampleWaves)];
   __shared__ float4 xs[kSampleN / 4];
   const int64_t N = P < kSampleN ? P : kSampleN;
   double v[3] = {0.0, 0.0, 0.0};  // sum tau, #zeros, #invalid over the sample
@@ -239,24 +271,81 @@ __global__ __launch_bounds__(kSampleThreads) void norm_sample_kernel(
       halley(s, g, -m[1] / s.Ps, m[2] / s.Ps);
       if (s.step <= kSampleTol) break;
     }
+    // a settled sample root is close enough for the exact phase's series step
+    if (s.step <= kSampleTol) s.phase = kNormPhaseExact;
   }
   s.lo = 0.0;
   s.hi = INFINITY;
   if (threadIdx.x == 0) *st_out = s;
 }
 
+// Root d of the degree-D Taylor model of g about A in the relative step
+// (A_new = A (1 + d)): sum_{n <= D} (-1)^n M_n d^n / n! = target, with the
+// scaled moments M_n = <(A tau)^n exp(-A tau)>, by Newton's method from d0;
+// NaN if it does not settle.
+template <int D>
+__device__ double taylor_root(const double (&M)[6], double target, double d0) {
+  double c[D + 1];
+  double f = 1.0;  // n!
+#pragma unroll
+  for (int n = 0; n <= D; ++n) {
+    if (n > 0) f *= (double)n;
+    c[n] = ((n & 1) ? -M[n] : M[n]) / f;
+  }
+  c[0] -= target;
+  double d = d0;
+#pragma unroll 1
+  for (int it = 0; it < 40; ++it) {
+    double p = c[D], dp = (double)D * c[D];
+#pragma unroll
+    for (int n = D - 1; n >= 1; --n) {
+      p = fma(p, d, c[n]);
+      dp = fma(dp, d, (double)n * c[n]);
+    }
+    p = fma(p, d, c[0]);
+    const double dn = d - p / dp;
+    if (!isfinite(dn)) return NAN;
+    if (fabs(dn - d) <= 1e-17) return dn;
+    d = dn;
+  }
+  return NAN;
+}
+
 // One step from full-pass moments (with the domain and root-existence checks
 // on the counts), and the phase change.
 __device__ NormState norm_step(NormState s, const double (&tot)[kNormQ]) {
-  if (tot[4] > 0.0) {
+  if (tot[kQBad] > 0.0) {
     s.done = 1;
     s.status |= LYAF_STATUS_DOMAIN;
     return s;
   }
-  if (!(tot[3] / s.P < s.target)) {
+  if (!(tot[kQZero] / s.P < s.target)) {
     s.done = 1;
     s.status |= LYAF_STATUS_NOROOT;
     return s;
+  }
+  if (s.phase == kNormPhaseExact) {
+    // the series of g about A: accepted at once when its degree-4 and
+    // degree-5 roots agree and the step is small
+    double M[6];
+    double An = 1.0;  // A^n
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      M[n] = An * tot[n] / s.P;
+      An *= s.A;
+    }
+    const double den = 2.0 * M[1] * M[1] - (M[0] - s.target) * M[2];
+    const double d0 = (den > 0.0) ? 2.0 * (M[0] - s.target) * M[1] / den : 0.0;  // Halley
+    const double d5 = taylor_root<5>(M, s.target, d0);
+    const double d4 = taylor_root<4>(M, s.target, d5);
+    if (fabs(d5) <= kTaylorMaxStep && fabs(d5 - d4) <= kTaylorAgree) {
+      const double Anew = s.A * (1.0 + d5);
+      s.step = fabs(Anew - s.A) / Anew;
+      s.A = Anew;
+      s.iter += 1;
+      s.done = 1;
+      return s;
+    }
   }
   halley(s, tot[0] / s.P - s.target, -tot[1] / s.P, tot[2] / s.P);
   // a step below kNormAcceptStep of A leaves an iterate within ~K 1e-15 of
@@ -279,7 +368,7 @@ __device__ NormState norm_step(NormState s, const double (&tot)[kNormQ]) {
 __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     const float *__restrict__ tau, int64_t P, double *partials, const NormState *st_prev,
     NormState *st_out, uint32_t *status) {
-  __shared__ double sh[kNormQ * kPassWaves];
+  __shared__ double sh[block_sum_lds(kNormQ, kPassWaves)];
   __shared__ NormState shs;
   if (threadIdx.x == 0) shs = *st_prev;
   __syncthreads();
@@ -308,7 +397,7 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t P4 = P >> 2;  // whole groups of four pixels; the tail below
-  double m[kNormQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double m[kNormQ] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int nz = 0, nbad = 0;
   auto counts = [&](float t) {
     nz += (t == 0.f);
@@ -351,13 +440,15 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     if (threadIdx.x < 64) tab[threadIdx.x] = exp_neg(threadIdx.x * (kLn2 / 64.0));
     __syncthreads();
     const double A = s.A;
-    auto px = [&](float tf) {
+    auto px = [&](float tf) {  // tau^n exp(-A tau), n = 0 .. 5
       const double t = (double)tf;
-      const double e = exp_neg_tab(A * t, tab);
-      const double te = t * e;
-      m[0] += e;
-      m[1] += te;
-      m[2] = fma(te, t, m[2]);
+      double te = exp_neg_tab(A * t, tab);
+      m[0] += te;
+#pragma unroll
+      for (int n = 1; n < 6; ++n) {
+        te *= t;
+        m[n] += te;
+      }
       counts(tf);
     };
     for (int64_t i = gtid; i < P4; i += nthr) {
@@ -369,8 +460,8 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     }
     if (gtid < tail) px(tau[4 * P4 + gtid]);
   }
-  m[3] = (double)nz;
-  m[4] = (double)nbad;
+  m[kQZero] = (double)nz;
+  m[kQBad] = (double)nbad;
   block_sum<kNormQ, kPassWaves>(m, sh);
   double *out = partials + out_buf * kPartStride * kMaxPartialBlocks;
   if (threadIdx.x == 0) {
@@ -378,10 +469,12 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     for (int k = 0; k < kNormQ; ++k) out[blockIdx.x * kPartStride + k] = m[k];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    s.pending = 0;
-    s.buf = out_buf;
-    s.nparts = gridDim.x;
-    *st_out = s;
+    // from LDS: the state is not held in registers across the pass
+    NormState o = shs;
+    o.pending = 0;
+    o.buf = out_buf;
+    o.nparts = gridDim.x;
+    *st_out = o;
   }
 }
 
@@ -390,7 +483,7 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
 __global__ __launch_bounds__(kNormThreads) void norm_finalise_kernel(
     float *__restrict__ tau, float *__restrict__ F, int64_t P, const double *partials,
     const NormState *st_prev, NormState *st_out, double *A_dev, uint32_t *status) {
-  __shared__ double sh[kNormQ * kNormWaves];
+  __shared__ double sh[block_sum_lds(kNormQ, kNormWaves)];
   __shared__ NormState shs;
   if (threadIdx.x == 0) shs = *st_prev;
   __syncthreads();
@@ -486,8 +579,8 @@ hipError_t launch_norm(int64_t n_pix, float *tau, float *F, double target_F, dou
 
 // ---------------------------------------------------------------------------
 // Allocation-free variant: the root-find's scratch (the FP64 partials of two
-// passes and the 16384-pixel sample, the iteration states, and a status word
-// for callers that pass none) lives in one file-scope device array instead of
+// passes and room for the sample, the iteration states, and a status word for
+// callers that pass none) lives in one file-scope device array instead of
 // a workspace.  The passes use at most kMaxPartialBlocks workgroups and a
 // fixed sample whatever n_pix is, so this fixed size serves every batch.  In
 // host code `scratch` names a host-side stand-in, not device memory: the
@@ -547,7 +640,7 @@ __device__ __forceinline__ void fwd_F(double A, float t, float &ts, float &Fp) {
 __global__ __launch_bounds__(kNormThreads) void normbw_reduce_kernel(
     const float *__restrict__ tau, const double *A_dev, const float *__restrict__ gF,
     const float *__restrict__ gT, int64_t P, double *partials) {
-  __shared__ double sh[16];
+  __shared__ double sh[block_sum_lds(2, kNormWaves)];
   const double A = *A_dev;
   double v[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -568,7 +661,7 @@ __global__ __launch_bounds__(kNormThreads) void normbw_reduce_kernel(
 __global__ __launch_bounds__(kNormThreads) void normbw_ratio_kernel(int nblocks,
                                                                     const double *partials,
                                                                     double *ratio) {
-  __shared__ double sh[16];
+  __shared__ double sh[block_sum_lds(2, kNormWaves)];
   double tot[2];
   reduce_partials<2, kNormWaves>(partials, nblocks, tot, sh);
   if (threadIdx.x == 0) *ratio = (tot[1] != 0.0) ? tot[0] / tot[1] : 0.0;

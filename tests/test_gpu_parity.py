@@ -173,7 +173,7 @@ def test_normalise_status_no_root_and_domain():
     assert L.status_read() == 0        # read clears
 
 
-SAMPLE_N = 16384  # pixels the root-find's first stage sees: floor(k P / N), k < N
+SAMPLE_N = 8192  # pixels the root-find's first stage sees: floor(k P / N), k < N
 
 
 def _sample_blind(rng, P):
