@@ -86,7 +86,7 @@ extern "C" {
  * line narrower than sqrt(log2 e) pixel widths, b < 1.2 dv, falls back to
  * shape 0's arithmetic); 5: the recurrence over 8 targets per lane, 2048-pixel
  * tiles (two exp2 per eight pairs; fallback below b = 2.7 dv, and tiles whose
- * reach exceeds 252 pixels take the full-sum path). */
+ * reach exceeds 200 pixels take the full-sum path). */
 #define LYAF_NUM_SHAPES 6
 #define LYAF_FLAG_SHAPE(v) ((((uint32_t)(v)) + 1u) << 8)
 

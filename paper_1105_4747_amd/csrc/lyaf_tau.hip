@@ -510,15 +510,21 @@ struct SkewShape {
   static constexpr int kThreads = NWAVES * kWave;
   static constexpr int kTile = NWAVES * kSpan;
   // staged sources: tile + 2 RH with RH <= kMaxRH, so that four 4-wave
-  // workgroups of 1024 targets fit in the 160 KiB of LDS of a compute unit
-  // (three of 2048 targets, whose margin is smaller: tiles reaching further
-  // take the full-sum path)
-  static constexpr int kMaxRH = M == 8 ? 252 : kSkewMaxRH;
+  // workgroups fit in the 160 KiB of LDS of a compute unit (tiles reaching
+  // further take the full-sum path).  With 2048 targets the margin is smaller,
+  // the window bounds are kept per 8 sources instead of 4, and the offsets
+  // of a block of steps come from the VALU instead of a table in LDS.
+  static constexpr int kMaxRH = M == 8 ? 200 : kSkewMaxRH;
   static constexpr int kChunkS =
       kTile + 2 * kMaxRH > kChunk ? kTile + 2 * kMaxRH : kChunk;
   static constexpr int kPlane = kChunkS / 4;
-  static constexpr int kGroups = kChunkS / kSkewGroup;
+  static constexpr int kGroup = M == 8 ? 8 : kSkewGroup;  // sources per window-bounds group
+  static constexpr int kGroups = kChunkS / kGroup;
+  static constexpr bool kFdTable = M != 8;
+  static constexpr int kFdEntries = kFdTable ? kFdN / 4 : 1;
   static_assert(kChunkS >= kChunk, "the full-sum path stages kChunk sources");
+  static_assert((kChunkS + 4) * 16 + kGroups * 4 + kFdEntries * 16 + 16 <= 160 * 1024 / 4,
+                "four workgroups per compute unit");
 };
 
 __device__ __forceinline__ int wave_max(int x) {
@@ -610,10 +616,10 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
           rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], a);
         }
       }
-      flo = stream_min<kSkewGroup>(flo);
-      fhi = stream_max<kSkewGroup>(fhi);
-      if ((threadIdx.x & (kSkewGroup - 1)) == 0 && c < cnt)
-        gwin[c / kSkewGroup] =
+      flo = stream_min<SH::kGroup>(flo);
+      fhi = stream_max<SH::kGroup>(fhi);
+      if ((threadIdx.x & (SH::kGroup - 1)) == 0 && c < cnt)
+        gwin[c / SH::kGroup] =
             (int)(((uint32_t)(int)fhi & 0xFFFFu) | ((uint32_t)(int)flo << 16));
     }
   }
@@ -633,9 +639,9 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   // above, its last position (source - lane start)
   int Hm = -(1 << 20), Em = -(1 << 20);
   {
-    const int g_beg = (T0r - RH) / kSkewGroup;
-    const int g_end = min((cnt + kSkewGroup - 1) / kSkewGroup,
-                          (T0r + SH::kSpan + RH + kSkewGroup - 1) / kSkewGroup);
+    constexpr int G = SH::kGroup;
+    const int g_beg = (T0r - RH) / G;
+    const int g_end = min((cnt + G - 1) / G, (T0r + SH::kSpan + RH + G - 1) / G);
     for (int g = g_beg + lane; g < g_end; g += kWave) {
       const int x = gwin[g];
       const int fh = (int)(int16_t)(x & 0xFFFF) - T0r;  // floor(hi) - T0r
@@ -643,8 +649,8 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       const int lhi = min(fh >> SH::kLgM, last_lane);  // last lane whose targets the windows meet
       const int llo = max((fl + M - 1) >> SH::kLgM, 0);  // first such lane
       if (llo <= lhi) {
-        Hm = max(Hm, T0r + M * lhi - kSkewGroup * g);
-        Em = max(Em, kSkewGroup * g + kSkewGroup - 1 - T0r - M * llo);
+        Hm = max(Hm, T0r + M * lhi - G * g);
+        Em = max(Em, G * g + G - 1 - T0r - M * llo);
       }
     }
     Hm = __builtin_amdgcn_readfirstlane(wave_max(Hm));
@@ -737,7 +743,12 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       q[1] = p[blk + PL];
       q[2] = p[blk + 2 * PL];
       q[3] = p[blk + 3 * PL];
-      q[4] = pf[blk];
+      if constexpr (SH::kFdTable) {
+        q[4] = pf[blk];
+      } else {
+        const float f = (float)(H4 - 4 * blk);
+        q[4] = make_float4(f, f - 1.f, f - 2.f, f - 3.f);
+      }
     };
     const int nblk = NS >> 2;
     // the next block's records are read while this one is evaluated; the read
@@ -782,10 +793,11 @@ template <int NWAVES, bool REC, int M>
 __global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
                                                                   const int2 *__restrict__ items,
                                                                   float *__restrict__ tau) {
-  __shared__ float4 rec[SkewShape<NWAVES, M>::kChunkS + 4];
-  __shared__ int gwin[SkewShape<NWAVES, M>::kGroups];
-  __shared__ float4 fdt[kFdN / 4];
-  fill_offset_table(fdt);  // published by the barrier after staging
+  using SH = SkewShape<NWAVES, M>;
+  __shared__ float4 rec[SH::kChunkS + 4];
+  __shared__ int gwin[SH::kGroups];
+  __shared__ float4 fdt[SH::kFdEntries];
+  if (SH::kFdTable) fill_offset_table(fdt);  // published by the barrier after staging
   tau_skew_tile<NWAVES, REC, M>(b, items[blockIdx.x], tau, rec, gwin, fdt);
 }
 
@@ -793,14 +805,15 @@ __global__ __launch_bounds__(NWAVES * kWave) void tau_skew_kernel(Batch b,
 // grid form
 template <int NWAVES, bool REC, int M>
 __global__ __launch_bounds__(NWAVES * kWave)
-__attribute__((amdgpu_waves_per_eu(NWAVES == 4 && M == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
+__attribute__((amdgpu_waves_per_eu(NWAVES == 4 ? 4 : 3))) void tau_skew_persistent_kernel(
     Batch b, const int2 *__restrict__ items, int n_items, unsigned int *queue,
     float *__restrict__ tau) {
-  __shared__ float4 rec[SkewShape<NWAVES, M>::kChunkS + 4];
-  __shared__ int gwin[SkewShape<NWAVES, M>::kGroups];
-  __shared__ float4 fdt[kFdN / 4];
+  using SH = SkewShape<NWAVES, M>;
+  __shared__ float4 rec[SH::kChunkS + 4];
+  __shared__ int gwin[SH::kGroups];
+  __shared__ float4 fdt[SH::kFdEntries];
   __shared__ int next;
-  fill_offset_table(fdt);
+  if (SH::kFdTable) fill_offset_table(fdt);
   for (;;) {
     __syncthreads();  // the previous item is done with LDS and `next`
     if (threadIdx.x == 0) next = (int)atomicAdd(queue, (unsigned)kQueueGrab);
