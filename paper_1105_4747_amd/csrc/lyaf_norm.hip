@@ -305,7 +305,7 @@ __device__ double taylor_root(const double (&M)[6], double target, double d0) {
     p = fma(p, d, c[0]);
     const double dn = d - p / dp;
     if (!isfinite(dn)) return NAN;
-    if (fabs(dn - d) <= 1e-17) return dn;
+    if (fabs(dn - d) <= 4e-16 * fabs(dn) + 1e-300) return dn;  // settled to rounding
     d = dn;
   }
   return NAN;
@@ -440,25 +440,29 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     if (threadIdx.x < 64) tab[threadIdx.x] = exp_neg(threadIdx.x * (kLn2 / 64.0));
     __syncthreads();
     const double A = s.A;
-    auto px = [&](float tf) {  // tau^n exp(-A tau), n = 0 .. 5
+    auto px = [&](float tf, double (&acc)[6]) {  // tau^n exp(-A tau), n = 0 .. 5
       const double t = (double)tf;
       double te = exp_neg_tab(A * t, tab);
-      m[0] += te;
+      acc[0] += te;
 #pragma unroll
       for (int n = 1; n < 6; ++n) {
         te *= t;
-        m[n] += te;
+        acc[n] += te;
       }
       counts(tf);
     };
+    // two sets of sums, alternate pixels (shorter dependency chains)
+    double m1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, m2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t i = gtid; i < P4; i += nthr) {
       const float4 t = group(i);
-      px(t.x);
-      px(t.y);
-      px(t.z);
-      px(t.w);
+      px(t.x, m1);
+      px(t.y, m2);
+      px(t.z, m1);
+      px(t.w, m2);
     }
-    if (gtid < tail) px(tau[4 * P4 + gtid]);
+    if (gtid < tail) px(tau[4 * P4 + gtid], m1);
+#pragma unroll
+    for (int n = 0; n < 6; ++n) m[n] = m1[n] + m2[n];
   }
   m[kQZero] = (double)nz;
   m[kQBad] = (double)nbad;
