@@ -111,10 +111,11 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (AMD-published)
 HBM_PEAK_GBS = 8000.0
 
 
-def instrument_traffic(case):
-    """HBM bytes per instrument forward launch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE record, or None when the kernel sources changed
-    since the counters were taken."""
+def instrument_traffic(case, direction="per_case"):
+    """HBM bytes per instrument forward ("per_case") or backward
+    ("backward_per_case") launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, or None when the kernel sources changed since the
+    counters were taken."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "instrument_traffic.json")))
@@ -125,7 +126,7 @@ def instrument_traffic(case):
         h.update(open(os.path.join(ROOT, "paper_1105_4747_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
         return None
-    ent = rec["per_case"].get(case)
+    ent = rec.get(direction, {}).get(case)
     return None if ent is None else ent["traffic_bytes_per_launch"]
 
 
@@ -177,7 +178,9 @@ def instrument_case(L, torch, dev, fields, timed, reps, case, name, F, dvt, w, s
             "algorithmic_bytes": int(nbytes), "algorithmic_flops": flops,
             "hbm_GBs": round(nbytes / t_fwd / 1e9, 1),
             "fp64_TFLOPs": round(flops / t_fwd / 1e12, 3), "roofline": roof,
-            "kernel": "instrument_kernel"}
+            "kernel": "instrument_kernel",
+            "backward_kernel": "instrument_backward_skewer_kernel (skewers of at most 4096 bins)",
+            "backward_traffic": instrument_traffic(case, "backward_per_case")}
 
 
 def instrument_section(L, torch, dev, fields, timed, reps, F_c2, dvt_c2, w_c2):
