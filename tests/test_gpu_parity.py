@@ -203,6 +203,28 @@ def test_normalise_sample_sees_only_zeros():
         assert st == L.STATUS_NOCONV
 
 
+@pytest.mark.parametrize("other", [1.08, 1.2, 1.6])
+def test_normalise_from_a_biased_sample(other):
+    """Every sampled pixel (4k of P = 4 N) has tau = 1 and the others ``other``:
+    the sample's root settles away from the batch's by ~6 %, ~15 % and ~40 %.
+    The first full pass's series step is then taken (~6 %) or, past a tenth of
+    A, refused for Halley steps until a later series step is accepted; A must
+    reach the oracle's root with a clean status either way."""
+    import torch
+    from paper_1105_4747_amd import lyaf as L
+    P = 4 * SAMPLE_N
+    raw = np.full(P, other, np.float32)
+    raw[::4] = 1.0
+    L.status_read()
+    ts, F, A = gpu_normalise(torch.from_numpy(raw).to("cuda:0"), 0.8)
+    st = L.status_read()
+    A_ref, _ = O.mean_flux_A(raw.astype(np.float64), 0.8)
+    print(f"biased sample ({other}): A={float(A.cpu()):.15g} ref={A_ref:.15g} status={st}")
+    assert st == 0
+    assert abs(float(A.cpu()) / A_ref - 1) <= A_REL
+    assert np.allclose(ts.cpu().numpy(), float(A.cpu()) * raw, rtol=1e-7, atol=0)
+
+
 def test_normalise_root_and_domain_checks_cover_unsampled_pixels():
     """No root, or an invalid value, that only the pixels outside the sample
     reveal: the full passes report it."""
