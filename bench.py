@@ -101,9 +101,23 @@ def adjoint_section(L, torch, dev, fields, timed, reps, peak):
     t_bwd = timed(lambda: L.tau_backward(*d, w.offsets, g, gd, gv, gT, gg,
                                          window_k=w.window_k), reps)
     pairs = algorithmic_pairs(w)
+    # one interleaved autograd step: tau', F and A forward (implicit-A rescale),
+    # the loss sum (F - F_t)^2, and its gradients for Delta, v, T0 and gamma
+    dd = [x.clone().requires_grad_(i != 2) for i, x in enumerate(d)]  # all but dv
+    F_t = torch.rand(P, device=dev, generator=torch.Generator(device=dev).manual_seed(6))
+
+    def step():
+        for x in dd:
+            x.grad = None
+        _, F, _ = L.tau_flux(dd[0], dd[1], dd[3], dd[4], dd[2], w.offsets, w.target_F,
+                             tau_ref=w.tau_ref, delta_pivot=w.delta_pivot, window_k=w.window_k)
+        ((F - F_t) ** 2).sum().backward()
+    t_step = timed(step, reps)
     out = {"workload": w.name, "n_pix": P, "tau_backward_ms": round(t_bwd * 1e3, 4),
            "tau_forward_ms": round(t_fwd * 1e3, 4), "pairs_per_px": round(pairs / P, 2),
-           "adjoint_pair_rate_per_s": pairs / t_bwd, "px_per_s": P / t_bwd}
+           "adjoint_pair_rate_per_s": pairs / t_bwd, "px_per_s": P / t_bwd,
+           "autograd_step_ms": round(t_step * 1e3, 4),
+           "autograd_step": "tau_flux forward + loss + backward (Delta, v, T0, gamma)"}
     return out
 
 
