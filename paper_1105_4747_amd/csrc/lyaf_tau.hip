@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lyaf_internal.h"
 
@@ -697,8 +698,10 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
         acc[k] = first ? q.x * E : __builtin_fmaf(q.x, E, acc[k]);
       }
     };
-    auto block = [&](const float4 (&q)[5], const bool first) {
-      if (REC && chain) {
+    // CH: the recurrence (decided per tile, so the whole walk takes one form
+    // and its sums stay in the same registers from block to block)
+    auto block = [&](auto ch, const float4 (&q)[5], const bool first) {
+      if constexpr (decltype(ch)::value) {
         pair_chain(q[0], q[4].x, first);
         pair_chain(q[1], q[4].y, false);
         pair_chain(q[2], q[4].z, false);
@@ -711,7 +714,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
           __builtin_amdgcn_sched_group_barrier(0x002, M == 8 ? 14 : 7, 0);  // VALU
         }
         return;
-      }
+      } else {
       pair_step(q[0], q[4].x, first);
       pair_step(q[1], q[4].y, false);
       pair_step(q[2], q[4].z, false);
@@ -723,6 +726,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       for (int z = 0; z < 4 * M; ++z) {
         __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
         __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // four VALU
+      }
       }
     };
     auto fold = [&]() {
@@ -753,26 +757,36 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     const int nblk = NS >> 2;
     // the next block's records are read while this one is evaluated; the read
     // past the last block stays inside the staged array
-    float4 qa[5], qb[5];
-    load(qa, 0);
-    int blk = 0;
-    for (; blk + 4 <= nblk; blk += 4) {
-      load(qb, blk + 1);
-      block(qa, true);
-      load(qa, blk + 2);
-      block(qb, false);
-      load(qb, blk + 3);
-      block(qa, false);
-      load(qa, blk + 4);
-      block(qb, false);
-      fold();
-    }
-    for (; blk < nblk; ++blk) {
-      load(qb, blk + 1);
-      block(qa, true);
-      fold();
+    auto walk = [&](auto ch) {
+      float4 qa[5], qb[5];
+      load(qa, 0);
+      int blk = 0;
+      for (; blk + 4 <= nblk; blk += 4) {
+        load(qb, blk + 1);
+        block(ch, qa, true);
+        load(qa, blk + 2);
+        block(ch, qb, false);
+        load(qb, blk + 3);
+        block(ch, qa, false);
+        load(qa, blk + 4);
+        block(ch, qb, false);
+        fold();
+      }
+      for (; blk < nblk; ++blk) {
+        load(qb, blk + 1);
+        block(ch, qa, true);
+        fold();
 #pragma unroll
-      for (int k = 0; k < 5; ++k) qa[k] = qb[k];
+        for (int k = 0; k < 5; ++k) qa[k] = qb[k];
+      }
+    };
+    if constexpr (REC) {
+      if (chain)
+        walk(std::true_type{});
+      else
+        walk(std::false_type{});
+    } else {
+      walk(std::false_type{});
     }
   }
 #pragma unroll
