@@ -14,8 +14,9 @@
 //                       uniform over the wave and come from the window bounds
 //                       of the sources that meet the wave's 256 targets.  Per
 //                       source and lane: one exact FMA for the velocity
-//                       offset, one exp2 per pair, FP32 sums with a blocked
-//                       Kahan fold every 16 terms; no cross-lane reduction.
+//                       offset, one exp2 per pair, FP32 sums in three levels
+//                       (blocks of 16 terms, partial sums of 8 blocks, their
+//                       sum); no cross-lane reduction.
 //   tau_window_kernel   the earlier shared-run form: a wave splits into S
 //                       source streams that share a sub-tile of 64 M / S
 //                       targets, visits the contiguous run of source groups
@@ -489,7 +490,8 @@ __global__ void reset_queue_kernel(unsigned int *queue) { *queue = 0u; }
 // conflicts) and the four steps of an unrolled block use immediate offsets.
 constexpr int kSkewM = 4;                  // targets per lane
 constexpr int kSkewSpan = kWave * kSkewM;  // targets per wave
-constexpr int kSkewFold = 16;              // Kahan fold period (terms per run)
+constexpr int kSkewFold = 16;              // terms per block sum of a run
+constexpr int kSkewPart = 8;               // block sums per partial sum
 constexpr int kSkewMargin = 12;            // staged sources beyond the reach
 constexpr int kSkewGroup = 4;              // sources per window-bounds group
 // Target-minus-source offsets as exact floats, read from LDS four at a time
@@ -663,9 +665,12 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   const int NS = min((H4 + Em + 1 + 3) & ~3, H4 + RH + M);
   const int i_l = t0 + M * lane;
 
-  float sum[M], comp[M];
+  // sums of a lane's targets in three levels: acc over a block of kSkewFold
+  // steps, part over up to kSkewPart blocks, sum over those (all terms are
+  // positive: a relative error of at most (15 + 7 + NS / 128) u)
+  float sum[M], part[M];
 #pragma unroll
-  for (int k = 0; k < M; ++k) sum[k] = comp[k] = 0.f;
+  for (int k = 0; k < M; ++k) sum[k] = part[k] = 0.f;
   if (Em >= -(1 << 19) && NS > 0) {
     const float dv = K.dv;
     float acc[M];
@@ -729,13 +734,17 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       }
       }
     };
+    int folds = 0;
     auto fold = [&]() {
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const float y = acc[k] - comp[k];
-        const float tt = sum[k] + y;
-        comp[k] = (tt - sum[k]) - y;
-        sum[k] = tt;
+      for (int k = 0; k < M; ++k) part[k] += acc[k];
+      if (++folds == kSkewPart) {
+        folds = 0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          sum[k] += part[k];
+          part[k] = 0.f;
+        }
       }
     };
     // column of the run's first source in every plane; a block is 4 steps
@@ -792,7 +801,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const int i = i_l + k;
-    if (i < i_end) tau[off + i] = sum[k] - comp[k];
+    if (i < i_end) tau[off + i] = sum[k] + part[k];
   }
 }
 
