@@ -711,12 +711,12 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
         pair_chain(q[1], q[4].y, false);
         pair_chain(q[2], q[4].z, false);
         pair_chain(q[3], q[4].w, false);
-        // the block's 8 exps, one per 7 (M = 4) or 14 (M = 8) other VALU
-        // instructions
+        // the block's 8 exps, one per 7 (M = 4) or 18 (M = 8: the last ones
+        // early, measured best) other VALU instructions
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
           __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);            // one transcendental
-          __builtin_amdgcn_sched_group_barrier(0x002, M == 8 ? 14 : 7, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x002, M == 8 ? 18 : 7, 0);  // VALU
         }
         return;
       } else {
