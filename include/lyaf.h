@@ -415,8 +415,10 @@ int lyaf_status_read(void *stream, uint32_t *device_status);
  * launch site of the entry points then records a pair of HIP events on the
  * caller's stream around its kernels, under one of the names
  *   "reach"      the per-skewer constants and reach pass (lyaf_tau, lyaf_tau_backward)
- *   "tau"        the windowed tau kernel of lyaf_tau (with the queue reset of a
- *                persistent launch); "tau_plain" the plain full-sum kernels
+ *   "tau"        the windowed tau kernel of lyaf_tau (one-launch grid form: the
+ *                events are set by the runtime at the kernel's own start and end,
+ *                hipExtLaunchKernel; persistent form: around the queue reset and
+ *                the kernel); "tau_plain" the plain full-sum kernels
  *   "normalise", "normalise_backward", "tau_adjoint", "instrument",
  *   "instrument_backward", "flux_pdf", "flux_power",
  *   "field_ky", "field_kx", "field_z" (the three kernels of lyaf_field_skewers),

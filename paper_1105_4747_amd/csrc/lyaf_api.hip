@@ -96,6 +96,27 @@ hipError_t timed(const char *name, hipStream_t st, F &&launch) {
   return hipSuccess;
 }
 
+// As timed(), for a launch that takes the events itself and has the runtime
+// set them at its kernel's own start and end (hipExtLaunchKernel): no launch
+// gap enters the time.  launch(nullptr, nullptr) when not timing.
+template <typename F>
+hipError_t timed_kernel(const char *name, hipStream_t st, F &&launch) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!g_kt.on || g_kt.rec.size() >= kMaxTimedLaunches ||
+      hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return launch(nullptr, nullptr);
+  hipEvent_t a = timer_event(), b = timer_event();
+  if (!a || !b) {
+    if (a) g_kt.pool.push_back(a);
+    if (b) g_kt.pool.push_back(b);
+    return launch(nullptr, nullptr);
+  }
+  hipError_t e = launch(a, b);
+  if (e != hipSuccess) return e;
+  g_kt.rec.push_back({name, a, b});
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t grow_dev(T *&p, int64_t &cap, int64_t need) {
   if (need <= cap) return hipSuccess;
@@ -575,8 +596,10 @@ int lyaf_tau(const lyaf_skewers *sk, const lyaf_params *prm, float *tau_out, voi
       return launch_tau_window(b, hp->d_items, hp->n_items, tau_out, st, variant, pg, ws->queue);
     });
   } else {
-    e = timed("tau", st,
-              [&] { return launch_tau_window(b, hp->d_items, hp->n_items, tau_out, st, variant); });
+    e = timed_kernel("tau", st, [&](hipEvent_t e0, hipEvent_t e1) {
+      return launch_tau_window(b, hp->d_items, hp->n_items, tau_out, st, variant, 0, nullptr, e0,
+                               e1);
+    });
   }
   return map_err(e);
 }

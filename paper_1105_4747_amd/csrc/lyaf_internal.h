@@ -127,9 +127,12 @@ extern const TauVariant kTauVariants[kNumTauVariants];
 
 // persistent_grid > 0 launches the persistent work-queue form with that many
 // workgroups (queue: a device counter, reset by a kernel inside the launch).
+// start / stop (grid form only, not under stream capture): events that the
+// runtime sets at the kernel's own start and end (hipExtLaunchKernel).
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items,
                              float *tau, hipStream_t st, int variant = kTauVariantDefault,
-                             int persistent_grid = 0, unsigned int *queue = nullptr);
+                             int persistent_grid = 0, unsigned int *queue = nullptr,
+                             hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Resident workgroups of the persistent form on the current device.
 int tau_persistent_grid(int variant);
 hipError_t launch_tau_plain(const Batch &b, int64_t skewer, int64_t n, float *tau,

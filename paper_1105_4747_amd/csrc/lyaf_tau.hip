@@ -31,6 +31,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "lyaf_internal.h"
 
 namespace lyaf {
@@ -856,7 +858,8 @@ struct VariantFns {
   const void *grid_fn;
   const void *pers_fn;
   int threads;
-  void (*grid)(const Batch &, const int2 *, int64_t, float *, hipStream_t);
+  void (*grid)(const Batch &, const int2 *, int64_t, float *, hipStream_t, hipEvent_t,
+               hipEvent_t);
   void (*pers)(const Batch &, const int2 *, int64_t, unsigned int *, int, float *, hipStream_t);
 };
 
@@ -866,9 +869,14 @@ VariantFns make_variant() {
   v.grid_fn = reinterpret_cast<const void *>(&tau_window_kernel<S, M, TILE>);
   v.pers_fn = reinterpret_cast<const void *>(&tau_window_persistent_kernel<S, M, TILE>);
   v.threads = kTauThreads;
-  v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
-    hipLaunchKernelGGL((tau_window_kernel<S, M, TILE>), dim3((unsigned)n), dim3(kTauThreads), 0,
-                       st, b, items, tau);
+  v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st,
+              hipEvent_t e0, hipEvent_t e1) {
+    if (e0)
+      hipExtLaunchKernelGGL((tau_window_kernel<S, M, TILE>), dim3((unsigned)n), dim3(kTauThreads),
+                            0, st, e0, e1, 0, b, items, tau);
+    else
+      hipLaunchKernelGGL((tau_window_kernel<S, M, TILE>), dim3((unsigned)n), dim3(kTauThreads),
+                         0, st, b, items, tau);
   };
   v.pers = [](const Batch &b, const int2 *items, int64_t n, unsigned int *queue, int grid,
               float *tau, hipStream_t st) {
@@ -886,9 +894,14 @@ VariantFns make_skew_variant() {
   v.grid_fn = reinterpret_cast<const void *>(&tau_skew_kernel<NWAVES, REC, M>);
   v.pers_fn = reinterpret_cast<const void *>(&tau_skew_persistent_kernel<NWAVES, REC, M>);
   v.threads = NT;
-  v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st) {
-    hipLaunchKernelGGL((tau_skew_kernel<NWAVES, REC, M>), dim3((unsigned)n), dim3(NT), 0, st, b,
-                       items, tau);
+  v.grid = [](const Batch &b, const int2 *items, int64_t n, float *tau, hipStream_t st,
+              hipEvent_t e0, hipEvent_t e1) {
+    if (e0)
+      hipExtLaunchKernelGGL((tau_skew_kernel<NWAVES, REC, M>), dim3((unsigned)n), dim3(NT), 0,
+                            st, e0, e1, 0, b, items, tau);
+    else
+      hipLaunchKernelGGL((tau_skew_kernel<NWAVES, REC, M>), dim3((unsigned)n), dim3(NT), 0, st,
+                         b, items, tau);
   };
   v.pers = [](const Batch &b, const int2 *items, int64_t n, unsigned int *queue, int grid,
               float *tau, hipStream_t st) {
@@ -918,13 +931,13 @@ const TauVariant kTauVariants[kNumTauVariants] = {
 
 hipError_t launch_tau_window(const Batch &b, const int2 *items, int64_t n_items, float *tau,
                              hipStream_t st, int variant, int persistent_grid,
-                             unsigned int *queue) {
+                             unsigned int *queue, hipEvent_t start, hipEvent_t stop) {
   if (n_items == 0) return hipSuccess;
   const VariantFns &f = variant_fns(variant);
   if (persistent_grid > 0)
     f.pers(b, items, n_items, queue, persistent_grid, tau, st);
   else
-    f.grid(b, items, n_items, tau, st);
+    f.grid(b, items, n_items, tau, st, start, stop);
   return hipGetLastError();
 }
 
