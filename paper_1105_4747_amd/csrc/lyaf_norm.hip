@@ -153,6 +153,7 @@ constexpr int kNormThreads = 256;  // backward kernels and finalise
 constexpr int kNormWaves = kNormThreads / kWave;
 constexpr int kPassThreads = 512;  // full root-find passes
 constexpr int kPassWaves = kPassThreads / kWave;
+constexpr int kPassBatch = 4;    // float4 reads in flight per thread in a pass
 // per-workgroup partials of a pass: S_0 .. S_5, #(tau = 0), #(invalid tau)
 constexpr int kNormQ = 8;
 constexpr int kQZero = 6, kQBad = 7;
@@ -408,6 +409,20 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     return make_float4(tau[4 * i], tau[4 * i + 1], tau[4 * i + 2], tau[4 * i + 3]);
   };
   const int64_t tail = P - 4 * P4;  // 0..3 pixels, one per thread of the first threads
+  // this thread's groups gtid, gtid + nthr, ...: kPassBatch reads issued
+  // before any is used, so that their latency overlaps the arithmetic of the
+  // others, then the rest one at a time
+  auto strided = [&](auto &&use) {
+    int64_t i = gtid;
+    for (; i + (kPassBatch - 1) * nthr < P4; i += kPassBatch * nthr) {
+      float4 t[kPassBatch];
+#pragma unroll
+      for (int b = 0; b < kPassBatch; ++b) t[b] = group(i + b * nthr);
+#pragma unroll
+      for (int b = 0; b < kPassBatch; ++b) use(t[b]);
+    }
+    for (; i < P4; i += nthr) use(group(i));
+  };
   if (s.phase == kNormPhaseFP32) {
     const float Al = (float)(s.A * kLog2e);
     float e0 = 0.f, e1 = 0.f, e2 = 0.f;
@@ -418,8 +433,7 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
       e2 = __builtin_fmaf(t * t, e, e2);
       counts(t);
     };
-    for (int64_t i = gtid; i < P4; i += nthr) {
-      const float4 t = group(i);
+    auto quad = [&](const float4 t) {
       px(t.x);
       px(t.y);
       px(t.z);
@@ -428,7 +442,8 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
       m[1] += (double)e1;
       m[2] += (double)e2;
       e0 = e1 = e2 = 0.f;
-    }
+    };
+    strided(quad);
     if (gtid < tail) {
       px(tau[4 * P4 + gtid]);
       m[0] += (double)e0;
@@ -453,13 +468,12 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
     };
     // two sets of sums, alternate pixels (shorter dependency chains)
     double m1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, m2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = gtid; i < P4; i += nthr) {
-      const float4 t = group(i);
+    strided([&](const float4 t) {
       px(t.x, m1);
       px(t.y, m2);
       px(t.z, m1);
       px(t.w, m2);
-    }
+    });
     if (gtid < tail) px(tau[4 * P4 + gtid], m1);
 #pragma unroll
     for (int n = 0; n < 6; ++n) m[n] = m1[n] + m2[n];
