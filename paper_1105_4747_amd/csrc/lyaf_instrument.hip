@@ -36,9 +36,10 @@
 // those values (the taps are even in m).  Skewers with at most kInsBwdBins
 // bins take one workgroup each, which forms the bins' FP64 prefix sums once in
 // LDS (a pixel's gathered gradient is then the difference of their linear
-// interpolation at its two edges) and walks the skewer's tiles; skewers with
-// more bins take one workgroup per tile and gather by a merge walk over the
-// bins in memory.
+// interpolation at its two edges) and walks the skewer's tiles, gathering a
+// row of 8 staged pixels per thread and the few rows past one per thread a
+// pixel per thread; skewers with more bins take one workgroup per tile and
+// gather by a merge walk over the bins in memory.
 #include <algorithm>
 
 #include "lyaf_internal.h"
@@ -684,9 +685,13 @@ struct InsBwdSkShared {
 constexpr int kBwdPerThread = kInsBwdBins / kInsThreads;  // bins per thread in the prefix sums
 static_assert(kBwdPerThread * kInsThreads == kInsBwdBins, "the prefix sums cover every bin");
 static_assert(64 + kInsTapBlock / 8 <= 128, "a wave's staged rows are two per lane at most");
+static_assert((kInsTile + kInsTapBlock) / 8 <= kInsThreads + kInsThreads / 8,
+              "the staged rows past one per thread are at most one pixel per thread");
 
-__global__ __launch_bounds__(kInsThreads) void instrument_backward_skewer_kernel(
-    InsArgs a, const int2 *__restrict__ items) {
+// Four waves per SIMD (at most 128 VGPRs), as many as the LDS of a skewer
+// with up to ~2700 bins leaves room for.
+__global__ __launch_bounds__(kInsThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+instrument_backward_skewer_kernel(InsArgs a, const int2 *__restrict__ items) {
   __shared__ InsBwdSkShared sh;
   extern __shared__ double P[];  // n_out + 1 prefix sums
   const InsSkewer k = ins_skewer(a, items[blockIdx.x].x);
@@ -761,47 +766,69 @@ __global__ __launch_bounds__(kInsThreads) void instrument_backward_skewer_kernel
       // staged offset x is pixel (p0 - M + u0 + x) mod n
       const uint32_t base = (uint32_t)wrap_index(p0 - k.M + u0, (int)k.n);
       const int rows = (span + tbp - 1 + 7) >> 3;  // staged offsets read by outputs < span
-      for (int r = threadIdx.x; r < rows; r += kInsThreads) {
-        // staged offsets 8r .. 8r + 7: pixels consecutive up to the end of the box
-        uint32_t i = base + 8u * (uint32_t)r;
-        if (i >= n32) i -= n32;
-        if (i >= n32) i %= n32;
-        int done = 0;
-        bool any = false;
-        while (done < 8) {
-          const int cnt = min(8 - done, (int)(n32 - i));
-          double G[8];
+      // the gathered gradients of cnt consecutive pixels from pixel i (no wrap
+      // inside the run), at staged offsets x0 .. x0 + cnt - 1; true if any is
+      // nonzero
+      const auto gather = [&](const uint32_t i, const int cnt, const int x0) -> bool {
+        double G[8];
 #pragma unroll
-          for (int p = 0; p < 8; ++p) G[p] = 0.0;
-          // images y = i + L n of the run's pixels that meet [x_first, x_last)
-          const double L_lo = ceil((x_first - (double)(i + cnt - 1) - 1.0) * inv_nd);
-          const double L_hi = floor((x_last - (double)i) * inv_nd);
-          for (double L = L_lo; L <= L_hi; L += 1.0) {
-            const double y0 = __builtin_fma(L, nd, (double)i);
-            double c0 = cum(y0);
-#pragma unroll
-            for (int p = 0; p < 8; ++p) {
-              if (p < cnt) {
-                const double c1 = cum(y0 + (double)(p + 1));
-                G[p] += c1 - c0;
-                c0 = c1;
-              }
-            }
-          }
-          const int x0 = 8 * r + done;
+        for (int p = 0; p < 8; ++p) G[p] = 0.0;
+        // images y = i + L n of the run's pixels that meet [x_first, x_last)
+        const double L_lo = ceil((x_first - (double)(i + cnt - 1) - 1.0) * inv_nd);
+        const double L_hi = floor((x_last - (double)i) * inv_nd);
+        for (double L = L_lo; L <= L_hi; L += 1.0) {
+          const double y0 = __builtin_fma(L, nd, (double)i);
+          double c0 = cum(y0);
 #pragma unroll
           for (int p = 0; p < 8; ++p) {
             if (p < cnt) {
-              const int x = x0 + p;
-              const float gv = (float)G[p];
-              any |= gv != 0.0f;
-              sh.f[(x & 7) * kDmaRows + (x >> 3)] = gv;
+              const double c1 = cum(y0 + (double)(p + 1));
+              G[p] += c1 - c0;
+              c0 = c1;
             }
           }
+        }
+        bool any = false;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          if (p < cnt) {
+            const int x = x0 + p;
+            const float gv = (float)G[p];
+            any |= gv != 0.0f;
+            sh.f[(x & 7) * kDmaRows + (x >> 3)] = gv;
+          }
+        }
+        return any;
+      };
+      const auto wrap_px = [&](uint32_t i) {
+        if (i >= n32) i -= n32;
+        if (i >= n32) i %= n32;
+        return i;
+      };
+      // staged offsets 8r .. 8r + 7 (pixels consecutive up to the end of the
+      // box) for the first kInsThreads rows, one row per thread; the rows past
+      // those (rows <= kInsThreads + kInsTapBlock / 8) one pixel per thread, so
+      // that no thread gathers two rows while the others wait at the barrier
+      if ((int)threadIdx.x < rows) {
+        const int r = threadIdx.x;
+        uint32_t i = wrap_px(base + 8u * (uint32_t)r);
+        int done = 0;
+        bool any = false;
+        while (done < 8) {  // a box shorter than the row wraps more than once
+          const int cnt = min(8 - done, (int)(n32 - i));
+          any |= gather(i, cnt, 8 * r + done);
           done += cnt;
           i = 0;
         }
         sh.nz_row[r] = any ? 1 : 0;
+      }
+      if (rows > kInsThreads) {
+        const int x = 8 * kInsThreads + (int)threadIdx.x;  // one pixel
+        const bool in = x < 8 * rows;
+        const bool nz = in && gather(wrap_px(base + (uint32_t)x), 1, x);
+        // a row's 8 pixels sit on 8 consecutive lanes of one wave
+        const uint64_t bal = __ballot(nz);
+        if (in && (lane & 7) == 0) sh.nz_row[x >> 3] = ((bal >> (lane & ~7)) & 0xFFu) ? 1 : 0;
       }
       __syncthreads();
       // rows 64 w .. 64 w + 63 + tbp / 8 feed wave w's outputs
