@@ -541,8 +541,11 @@ __device__ __forceinline__ int wave_max(int x) {
 // REC: the Gaussian recurrence across a lane's four targets.  With
 // t_k = t_0 + k a (a = dv r), t_k^2 - t_(k-1)^2 = a (2 t_(k-1) + a), so
 // E_k = exp2(-t_k^2) = E_(k-1) G_(k-1) with G_0 = exp2(-a (2 t_0 + a)) and
-// G_k = G_(k-1) C, C = exp2(-2 a^2) per source (staged in place of a, which is
-// then dv r): two exp2 per source and lane instead of four.  The chain starts
+// G_k = G_(k-1) C, C = exp2(-2 a^2) per source: two exp2 per source and lane
+// instead of four.  These records hold (w, a, v r, C), so that
+// t_0 = (fd dv - v) r = fd a - v r is one FMA on the exact offset fd; a and
+// v r are rounded once each, which adds about u (|fd a| + |v r|) to t_0 (on the
+// 4096 x 4096 workload's fields, 1e-7 of tau at most).  The chain starts
 // at the lane's first target; it is exact to rounding unless E_0 underflows
 // while a later E_k matters, which needs a > 1.16 (|t_0| > 11.2 and
 // |t_0 + 3a| < 7.75), so a tile with any source of a > kRecMaxA (unresolved
@@ -616,7 +619,8 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
         const float a = K.dv * o.r;
         if (REC) {
           unsafe |= (o.w > 0.f) && !(a <= (M == 8 ? kRecMaxA8 : kRecMaxA));
-          rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], fexp2(-2.f * a * a));
+          // (w, a = dv r, v r, C): t_0 = fd a - v r takes one FMA in the walk
+          rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, a, vv[u] * o.r, fexp2(-2.f * a * a));
         } else {
           rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], a);
         }
@@ -679,9 +683,10 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     // one source against the lane's kSkewM targets; fd is the exact target
     // minus source offset of the step; FIRST starts a new run
     auto pair_step = [&](const float4 q, const float fd, const bool first) {
-      const float d0 = __builtin_fmaf(fd, dv, -q.z);
-      const float tt0 = d0 * q.y;
-      const float a = REC ? dv * q.y : q.w;  // REC records hold C in .w
+      // REC records hold (w, a, v r, C), the others (w, r, v, a)
+      const float tt0 =
+          REC ? __builtin_fmaf(fd, q.y, -q.z) : __builtin_fmaf(fd, dv, -q.z) * q.y;
+      const float a = REC ? q.y : q.w;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, a, tt0);
@@ -691,9 +696,8 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     };
     // one source against the lane's kSkewM targets by the recurrence
     auto pair_chain = [&](const float4 q, const float fd, const bool first) {
-      const float d0 = __builtin_fmaf(fd, dv, -q.z);
-      const float tt0 = d0 * q.y;
-      const float a = dv * q.y;
+      const float tt0 = __builtin_fmaf(fd, q.y, -q.z);
+      const float a = q.y;
       float E = fexp2(-(tt0 * tt0));
       float G = fexp2(fminf(-(__builtin_fmaf(2.f, tt0, a) * a), 64.f));
 #pragma unroll
