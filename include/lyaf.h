@@ -76,9 +76,10 @@ extern "C" {
 /* Persistent work-queue launch of the windowed kernel (see plans below). */
 #define LYAF_FLAG_PERSISTENT 4u
 /* Force windowed-kernel shape v (0 .. LYAF_NUM_SHAPES-1; the shapes a plan's
- * tuner chooses from): flags |= LYAF_FLAG_SHAPE(v).  Shape 0 is the default:
- * each lane owns 4 consecutive targets and walks its own run of sources, one
- * source stream per wave, 1024-pixel tiles; 1: the same with 512-pixel tiles;
+ * tuner chooses from): flags |= LYAF_FLAG_SHAPE(v); without the flag (and in
+ * a plan created without LYAF_PLAN_AUTOTUNE) shape 4 runs.  0: each lane owns
+ * 4 consecutive targets and walks its own run of sources, one source stream
+ * per wave, 1024-pixel tiles; 1: the same with 512-pixel tiles;
  * 2: 8 source streams share 32-target sub-tiles, 4 targets per lane,
  * 512-pixel tiles; 3: as 2 with 2 targets per lane; 4: as 0 with the
  * Gaussian of a source evaluated across the lane's 4 targets by a product

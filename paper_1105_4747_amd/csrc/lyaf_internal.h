@@ -122,7 +122,7 @@ struct TauVariant {
   int S, M, tile;
 };
 constexpr int kNumTauVariants = 6;
-constexpr int kTauVariantDefault = 0;
+constexpr int kTauVariantDefault = 4;  // shape used when no shape is forced or tuned
 extern const TauVariant kTauVariants[kNumTauVariants];
 
 // persistent_grid > 0 launches the persistent work-queue form with that many

@@ -4,10 +4,12 @@
 //   reach_kernel        one workgroup per skewer: per-skewer constants in FP64,
 //                       the largest velocity-space reach (|v_j| + k b_j) / dv in
 //                       pixels, and the device-side domain checks.
-//   tau_skew_kernel     one workgroup per tile of 1024 (or 512) targets; the
-//                       default form.  The sources that can reach the tile
+//   tau_skew_kernel     one workgroup per tile of 1024 (or 512, or 2048)
+//                       targets; with the recurrence below over 4 targets per
+//                       lane, the default shape.  The sources that can reach the tile
 //                       (tile +- reach) are staged once into LDS as
-//                       (w, r, v, a = dv r) in four planes by index mod 4,
+//                       (w, r, v, a = dv r), or (w, a, v r, C) for the
+//                       recurrence, in four planes by index mod 4,
 //                       with each source's window bounds.  A lane owns 4
 //                       consecutive targets and walks its own run of sources,
 //                       shifted with its targets, whose start and length are
@@ -588,53 +590,65 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
   const float pivot = b.pivot, wk = b.window_k;
   bool bad = false;
   int unsafe = 0;  // REC: a source of a > kRecMaxA
-  for (int c0 = 0; c0 < cnt; c0 += SIT * NT) {
-    float dd[SIT], vv[SIT];
+  // CHAIN_LAYOUT: records (w, a, v r, C) for the recurrence, else (w, r, v, a)
+  auto stage = [&](const bool chain_layout) {
+    for (int c0 = 0; c0 < cnt; c0 += SIT * NT) {
+      float dd[SIT], vv[SIT];
 #pragma unroll
-    for (int u = 0; u < SIT; ++u) {
-      const int c = c0 + threadIdx.x + u * NT;
-      dd[u] = 0.f;
-      vv[u] = 0.f;
-      if (c < cnt) {
-        const int e = e_lo + c;  // -n <= e < 2n: RH <= n/2 and i_end <= n
-        const int j = e < 0 ? e + n : (e >= n ? e - n : e);
-        dd[u] = b.delta[off + j];
-        vv[u] = b.vpec[off + j];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < SIT; ++u) {
-      if (c0 + u * NT >= cnt) break;
-      const int c = c0 + threadIdx.x + u * NT;
-      bad |= (c < cnt) && bad_delta(dd[u]);
-      const Src o = source_of(dd[u], K, pivot);
-      float flo = 8191.f, fhi = -8192.f;  // no window: meets no target
-      if (c < cnt) {
-        if (o.w > 0.f) {
-          const float cc = __builtin_fmaf(vv[u], K.inv_dv, (float)c);  // line centre
-          const float h = wk * o.b * K.inv_dv;                         // half window
-          flo = fminf(fmaxf(ceilf(cc - h), -8192.f), 8191.f);
-          fhi = fminf(fmaxf(floorf(cc + h), -8192.f), 8191.f);
-        }
-        const float a = K.dv * o.r;
-        if (REC) {
-          unsafe |= (o.w > 0.f) && !(a <= (M == 8 ? kRecMaxA8 : kRecMaxA));
-          // (w, a = dv r, v r, C): t_0 = fd a - v r takes one FMA in the walk
-          rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, a, vv[u] * o.r, fexp2(-2.f * a * a));
-        } else {
-          rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], a);
+      for (int u = 0; u < SIT; ++u) {
+        const int c = c0 + threadIdx.x + u * NT;
+        dd[u] = 0.f;
+        vv[u] = 0.f;
+        if (c < cnt) {
+          const int e = e_lo + c;  // -n <= e < 2n: RH <= n/2 and i_end <= n
+          const int j = e < 0 ? e + n : (e >= n ? e - n : e);
+          dd[u] = b.delta[off + j];
+          vv[u] = b.vpec[off + j];
         }
       }
-      flo = stream_min<SH::kGroup>(flo);
-      fhi = stream_max<SH::kGroup>(fhi);
-      if ((threadIdx.x & (SH::kGroup - 1)) == 0 && c < cnt)
-        gwin[c / SH::kGroup] =
-            (int)(((uint32_t)(int)fhi & 0xFFFFu) | ((uint32_t)(int)flo << 16));
+#pragma unroll
+      for (int u = 0; u < SIT; ++u) {
+        if (c0 + u * NT >= cnt) break;
+        const int c = c0 + threadIdx.x + u * NT;
+        bad |= (c < cnt) && bad_delta(dd[u]);
+        const Src o = source_of(dd[u], K, pivot);
+        float flo = 8191.f, fhi = -8192.f;  // no window: meets no target
+        if (c < cnt) {
+          if (o.w > 0.f) {
+            const float cc = __builtin_fmaf(vv[u], K.inv_dv, (float)c);  // line centre
+            const float h = wk * o.b * K.inv_dv;                         // half window
+            flo = fminf(fmaxf(ceilf(cc - h), -8192.f), 8191.f);
+            fhi = fminf(fmaxf(floorf(cc + h), -8192.f), 8191.f);
+          }
+          const float a = K.dv * o.r;
+          if (chain_layout) {
+            unsafe |= (o.w > 0.f) && !(a <= (M == 8 ? kRecMaxA8 : kRecMaxA));
+            // (w, a = dv r, v r, C): t_0 = fd a - v r takes one FMA in the walk
+            rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, a, vv[u] * o.r, fexp2(-2.f * a * a));
+          } else {
+            rec[(c & 3) * PL + (c >> 2)] = make_float4(o.w, o.r, vv[u], a);
+          }
+        }
+        flo = stream_min<SH::kGroup>(flo);
+        fhi = stream_max<SH::kGroup>(fhi);
+        if ((threadIdx.x & (SH::kGroup - 1)) == 0 && c < cnt)
+          gwin[c / SH::kGroup] =
+              (int)(((uint32_t)(int)fhi & 0xFFFFu) | ((uint32_t)(int)flo << 16));
+      }
     }
-  }
+  };
+  stage(REC);
   flag_bad_delta(b, bad);
   const bool chain = REC ? __syncthreads_or(unsafe) == 0 : false;
   if (!REC) __syncthreads();
+  if (REC && !chain) {
+    // the direct form keeps the exact offset d_0 = fd dv - v (one rounding)
+    // and r: narrow lines, whose wings can carry a pixel's whole tau, would
+    // otherwise take the rounding of v r at |v r| >> |t_0|.  The tile is
+    // staged again with those records (Delta and v re-read, mostly from L2).
+    stage(false);
+    __syncthreads();
+  }
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -683,10 +697,9 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
     // one source against the lane's kSkewM targets; fd is the exact target
     // minus source offset of the step; FIRST starts a new run
     auto pair_step = [&](const float4 q, const float fd, const bool first) {
-      // REC records hold (w, a, v r, C), the others (w, r, v, a)
-      const float tt0 =
-          REC ? __builtin_fmaf(fd, q.y, -q.z) : __builtin_fmaf(fd, dv, -q.z) * q.y;
-      const float a = REC ? q.y : q.w;
+      // records (w, r, v, a): the direct form of every shape
+      const float tt0 = __builtin_fmaf(fd, dv, -q.z) * q.y;
+      const float a = q.w;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const float t = (k == 0) ? tt0 : __builtin_fmaf((float)k, a, tt0);
@@ -918,11 +931,11 @@ VariantFns make_skew_variant() {
 
 const VariantFns &variant_fns(int v) {
   static const VariantFns table[kNumTauVariants] = {
-      make_skew_variant<4>(),      // kTauVariantDefault
+      make_skew_variant<4>(),
       make_skew_variant<2>(),
       make_variant<8, 4, 512>(),
       make_variant<8, 2, 512>(),
-      make_skew_variant<4, true>(),     // the Gaussian recurrence across a lane's targets
+      make_skew_variant<4, true>(),     // the recurrence across a lane's targets (default)
       make_skew_variant<4, true, 8>(),  // the same over 8 targets per lane
   };
   return table[v];
