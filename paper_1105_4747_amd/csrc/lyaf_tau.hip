@@ -493,7 +493,6 @@ __global__ void reset_queue_kernel(unsigned int *queue) { *queue = 0u; }
 // index mod 4, so the 64 lanes of a step read 64 consecutive float4 (no bank
 // conflicts) and the four steps of an unrolled block use immediate offsets.
 constexpr int kSkewM = 4;                  // targets per lane
-constexpr int kSkewSpan = kWave * kSkewM;  // targets per wave
 constexpr int kSkewFold = 16;              // terms per block sum of a run
 constexpr int kSkewPart = 8;               // block sums per partial sum
 constexpr int kSkewMargin = 12;            // staged sources beyond the reach
@@ -739,18 +738,18 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
         }
         return;
       } else {
-      pair_step(q[0], q[4].x, first);
-      pair_step(q[1], q[4].y, false);
-      pair_step(q[2], q[4].z, false);
-      pair_step(q[3], q[4].w, false);
-      // v_exp_f32 takes about two VALU issue slots and does not overlap other
-      // VALU work of the wave: spread the block's 16 exps, one per four other
-      // VALU instructions
+        pair_step(q[0], q[4].x, first);
+        pair_step(q[1], q[4].y, false);
+        pair_step(q[2], q[4].z, false);
+        pair_step(q[3], q[4].w, false);
+        // the transcendental unit runs beside the other VALU work: the
+        // block's 4 M exps are spread one per four other VALU instructions,
+        // so that they do not queue behind one another
 #pragma unroll
-      for (int z = 0; z < 4 * M; ++z) {
-        __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // four VALU
-      }
+        for (int z = 0; z < 4 * M; ++z) {
+          __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // one transcendental
+          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // four VALU
+        }
       }
     };
     int folds = 0;
@@ -783,6 +782,7 @@ __device__ __forceinline__ void tau_skew_tile(const Batch &b, const int2 item,
       }
     };
     const int nblk = NS >> 2;
+    static_assert(kSkewFold == 4 * 4, "the walk folds after four blocks of four steps");
     // the next block's records are read while this one is evaluated; the read
     // past the last block stays inside the staged array
     auto walk = [&](auto ch) {
