@@ -16,7 +16,7 @@
 //   norm_pass x3   S_k = sum tau^k exp(-A tau) over every pixel, in FP64 per
 //                  workgroup, with the counts of zero and invalid values.
 //                  After a settled sample the passes are exact from the
-//                  first: FP64 exponentials (to 1e-13), k = 0 .. 5.  Each
+//                  first: FP64 exponentials (to 2e-13), k = 0 .. 5.  Each
 //                  pass begins with every workgroup summing the previous
 //                  pass's partials in the same fixed order and taking the
 //                  same step: the root of the degree-5 Taylor series of g
@@ -79,24 +79,25 @@ __device__ __forceinline__ double exp_neg(double x) {
   return p * __hiloint2double((1023 - ki) << 20, 0);  // p 2^-k
 }
 
-// exp(-x) for x >= 0 to 1e-13 relative (the moments of the exact phase need
-// ~1e-10): x = (n/64) ln2 + r with |r| <= ln2/128, 2^(-n/64) =
-// 2^-(n >> 6) tab[n & 63] with tab[j] = 2^(-j/64), and exp(-r) by its Taylor
-// series to degree 4 (truncation below 4e-14).  Below 2^-1021 the result is 0.
+// exp(-x) for x >= 0 to 2e-13 relative (the moments of the exact phase need
+// ~1e-10): x = (n/256) ln2 + r with |r| <= ln2/512, 2^(-n/256) =
+// 2^-(n >> 8) tab[n & 255] with tab[j] = 2^(-j/256), and exp(-r) by its Taylor
+// series to degree 3 (truncation below 1.5e-13).  Branch-free: x is clamped at
+// 745 (NaN too) and the exponent field of 2^-(n >> 8) at zero, so the result
+// is 0 beyond x ~ 709 and below 2^-1021 from 708 on.
 __device__ __forceinline__ double exp_neg_tab(double x, const double *tab) {
-  const double xc = fmin(x, 708.0);  // branch-free: the select below returns 0
+  const double xc = fmin(x, 745.0);
   const double shifter = 6755399441055744.0;  // 1.5 2^52
-  const double t = fma(xc, 64.0 * kLog2e, shifter);
+  const double t = fma(xc, 256.0 * kLog2e, shifter);
   const double n = t - shifter;
   const int ni = __double2loint(t);
-  const double r = fma(-n, kLn2 / 64.0, xc);
-  double p = 1.0 / 24.0;
-  p = fma(p, -r, 1.0 / 6.0);
+  const double r = fma(-n, kLn2 / 256.0, xc);
+  double p = 1.0 / 6.0;
   p = fma(p, -r, 0.5);
   p = fma(p, -r, 1.0);
   p = fma(p, -r, 1.0);
-  const double e = tab[ni & 63] * p * __hiloint2double((1023 - (ni >> 6)) << 20, 0);
-  return (x <= 708.0) ? e : 0.0;
+  const int ex = max(1023 - (ni >> 8), 0);
+  return tab[ni & 255] * p * __hiloint2double(ex << 20, 0);
 }
 
 // Sum of N values over a workgroup of NW waves (fixed order), in every
@@ -451,8 +452,9 @@ __global__ __launch_bounds__(kPassThreads) void norm_pass_kernel(
       m[2] += (double)e2;
     }
   } else {
-    __shared__ double tab[64];  // 2^(-j/64)
-    if (threadIdx.x < 64) tab[threadIdx.x] = exp_neg(threadIdx.x * (kLn2 / 64.0));
+    __shared__ double tab[256];  // 2^(-j/256)
+    static_assert(kPassThreads >= 256, "one table entry per thread");
+    if (threadIdx.x < 256) tab[threadIdx.x] = exp_neg(threadIdx.x * (kLn2 / 256.0));
     __syncthreads();
     const double A = s.A;
     auto px = [&](float tf, double (&acc)[6]) {  // tau^n exp(-A tau), n = 0 .. 5
