@@ -570,7 +570,8 @@ def main():
     ap.add_argument("--tau-only", action="store_true",
                     help="only run lyaf_tau (reach + windowed kernel) K times, for profiling")
     ap.add_argument("--shape", type=int, default=None,
-                    help="windowed-kernel shape for --tau-only (LYAF_FLAG_SHAPE); default: 0")
+                    help="windowed-kernel shape for --tau-only (LYAF_FLAG_SHAPE); default: 4, "
+                         "the library's own default")
     ap.add_argument("--persistent", action="store_true", help="persistent launch in --tau-only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB float32 buffer 3 times (counter calibration)")
@@ -658,7 +659,7 @@ def main():
     A = torch.empty((), device=dev, dtype=torch.float64)
 
     if args.tau_only:
-        shape = 0 if args.shape is None else args.shape
+        shape = 4 if args.shape is None else args.shape
         fl = L.FLAG_SHAPE(shape) | (L.FLAG_PERSISTENT if args.persistent else 0)
         for _ in range(args.warmup + args.steps):
             L.tau(delta, vpec, dvt, T0, gamma, w.offsets, ts, tau_ref=w.tau_ref,
